@@ -1,0 +1,58 @@
+/*
+ * mpdata_oracle.h -- interface of the FP64 CPU oracle of one MPDATA step.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+ * baseline of the benchmark.  Shares no code with the HIP library.
+ */
+#ifndef MPDATA_ORACLE_H
+#define MPDATA_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OPEN = 1 };
+
+typedef struct {
+    int nx, ny, nz; /* cells along x (fastest), y, z */
+    int bc;         /* ORC_BC_PERIODIC or ORC_BC_OPEN */
+    int iord;       /* 1: donor cell only; 2: one corrective pass */
+    int nonos;      /* 1: non-oscillatory limiter on */
+    double eps;     /* regulariser of ratio denominators */
+} orc_params;
+
+/* Optional stage outputs of one step (any pointer may be NULL). */
+typedef struct {
+    double *psi1;               /* nx*ny*nz */
+    double *v1, *v2, *v3;       /* unlimited pseudo-velocities, face arrays */
+    double *mx, *mn;            /* limiter bounds */
+    double *beta_up, *beta_dn;  /* limiter factors */
+} orc_stages;
+
+/* 0 if the parameters are valid, -1 otherwise. */
+int orc_check(const orc_params *p);
+
+/* One step psi -> out.  Returns 0, -1 on bad parameters, -2 on allocation
+ * failure.  psi and out must not alias. */
+int orc_step(const orc_params *p, const double *psi, const double *u1,
+             const double *u2, const double *u3, const double *h, double *out,
+             orc_stages *stages);
+
+/* nsteps steps in place on psi. */
+int orc_run(const orc_params *p, double *psi, const double *u1, const double *u2,
+            const double *u3, const double *h, int nsteps);
+
+/* Compensated sum of h[i]*psi[i] (Ogita-Rump-Oishi Dot2). */
+double orc_mass(long n, const double *h, const double *psi);
+
+/* Net inflow of the first-order pass through the faces of an open domain. */
+double orc_open_inflow(const orc_params *p, const double *psi, const double *u1,
+                       const double *u2, const double *u3);
+
+/* Threads used by the stage loops. */
+int orc_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

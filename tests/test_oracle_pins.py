@@ -1,0 +1,348 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the mathematics.
+
+Nothing here compares the oracle with itself: every expected value comes
+from hand arithmetic, a closed form, an exact rational sum, an invariant of
+the scheme or its known order of accuracy.  Together they are chosen so that
+a plausible slip in any stage -- a dropped term, a wrong sign or index, a
+transposed operand -- fails at least one of them (the mutation test in
+``test_oracle_mutations.py`` plants such slips and checks that they do).
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_1507_01265_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U = 2.0 ** -53  # unit roundoff of binary64
+
+
+def _line(psi0, c=0.5):
+    n = len(psi0)
+    psi = np.array(psi0, dtype=np.float64).reshape(1, 1, n)
+    u1 = np.full((1, 1, n + 1), c)
+    return psi, u1, np.zeros((1, 2, n)), np.zeros((2, 1, n)), np.ones((1, 1, n))
+
+
+def _fr(xs):
+    return np.array([float(Fraction(x)) for x in xs])
+
+
+# ------------------------------------------------------------ hand arithmetic
+
+@pytest.mark.parametrize("case", json.load(open(os.path.join(GOLDEN, "hand_1d.json")))["cases"],
+                         ids=lambda c: c["name"])
+def test_hand_1d(orc, case):
+    """4-cell periodic line, u = 1/2: stage values and results against exact
+    rationals worked out by hand (tests/golden/hand_1d.json)."""
+    args = _line(_fr(case["psi0"]))
+    out, st = orc.step(*args, nonos=True, stages=True)
+    np.testing.assert_allclose(st["psi1"].ravel(), _fr(case["psi1"]), rtol=0, atol=1e-15)
+    if "v1_faces_0_to_4" in case:
+        np.testing.assert_allclose(st["v1"].ravel(), _fr(case["v1_faces_0_to_4"]), rtol=0,
+                                   atol=1e-14)
+    np.testing.assert_allclose(out.ravel(), _fr(case["psi_nonos"]), rtol=0, atol=1e-14)
+    out0 = orc.step(*args, nonos=False)
+    np.testing.assert_allclose(out0.ravel(), _fr(case["psi_no_limiter"]), rtol=0, atol=1e-14)
+
+
+def test_hand_1d_along_every_axis(orc):
+    """The same line laid along y and along z (other Courant numbers zero)
+    gives the same numbers: the 3-D scheme reduces to the 1-D one."""
+    ref = orc.step(*_line([1.0, 2.0, 3.0, 4.0]))
+    psi = np.array([1.0, 2.0, 3.0, 4.0])
+    # along y
+    out_y = orc.step(psi.reshape(1, 4, 1), np.zeros((1, 4, 2)), np.full((1, 5, 1), 0.5),
+                     np.zeros((2, 4, 1)), np.ones((1, 4, 1)))
+    # along z
+    out_z = orc.step(psi.reshape(4, 1, 1), np.zeros((4, 1, 2)), np.zeros((4, 2, 1)),
+                     np.full((5, 1, 1), 0.5), np.ones((4, 1, 1)))
+    np.testing.assert_array_equal(out_y.ravel(), ref.ravel())
+    np.testing.assert_array_equal(out_z.ravel(), ref.ravel())
+
+
+# ------------------------------------------------------ closed form (donor cell)
+
+@pytest.mark.parametrize("c", [(0.3, 0.2, 0.1), (-0.25, 0.4, -0.3), (0.0, -0.5, 0.45)])
+def test_donor_cell_fourier_closed_form(orc, c):
+    """iord = 1 with constant Courant numbers on a periodic grid is a linear
+    constant-coefficient scheme: each Fourier mode is multiplied per step by
+    g = 1 - sum_d [pos(C_d)(1 - e^{-i th_d}) + neg(C_d)(e^{i th_d} - 1)]."""
+    rng = np.random.default_rng(7)
+    shape = (6, 10, 12)
+    psi = rng.uniform(0.5, 1.5, shape)
+    u1, u2, u3 = inputs.constant_courant(shape, c)
+    nsteps = 5
+    out = orc.run(psi, u1, u2, u3, np.ones(shape), nsteps, iord=1)
+    th = [2 * np.pi * np.fft.fftfreq(n) for n in shape]
+    tz, ty, tx = np.meshgrid(*th, indexing="ij")
+    g = np.ones(shape, dtype=complex)
+    for cd, t in zip(c, (tx, ty, tz)):
+        g -= max(cd, 0.0) * (1 - np.exp(-1j * t)) + min(cd, 0.0) * (np.exp(1j * t) - 1)
+    want = np.fft.ifftn(np.fft.fftn(psi) * g ** nsteps).real
+    np.testing.assert_allclose(out, want, rtol=0, atol=1e-13)
+
+
+# ----------------------------------------------------------- exact shifts
+
+@pytest.mark.parametrize("axis,sign", [(2, 1), (2, -1), (1, 1), (1, -1), (0, 1), (0, -1)])
+@pytest.mark.parametrize("nonos", [True, False])
+def test_courant_one_is_an_exact_shift(orc, axis, sign, nonos):
+    """|C| = 1 along one axis, h = 1: the upwind pass moves psi by exactly one
+    cell, the pseudo-velocity vanishes (|U| - U^2/G = 0, no cross flow) and the
+    step is a bitwise roll for psi in [1, 2) (differences are exact there)."""
+    rng = np.random.default_rng(11)
+    shape = (5, 6, 7)
+    psi = rng.uniform(1.0, 2.0, shape)
+    c = [0.0, 0.0, 0.0]
+    c[2 - axis] = float(sign)
+    u1, u2, u3 = inputs.constant_courant(shape, c)
+    out = orc.step(psi, u1, u2, u3, np.ones(shape), nonos=nonos)
+    np.testing.assert_array_equal(out, np.roll(psi, sign, axis=axis))
+
+
+# ---------------------------------------------------------- constant field
+
+def _fields_for_constant(kind, shape, bc):
+    if kind == "constant":
+        u1, u2, u3 = inputs.constant_courant(shape, (0.21, -0.17, 0.33))
+        h = inputs.random_smooth(3, shape).h
+    elif kind == "rotation":
+        f = inputs.rotation(seed=5, shape=shape)
+        u1, u2, u3, h = f.u1, f.u2, f.u3, f.h
+    else:
+        f = inputs.random_smooth(9, shape, bc=bc, divergence_free=True, cmax=0.45)
+        u1, u2, u3, h = f.u1, f.u2, f.u3, f.h
+    return u1, u2, u3, h
+
+
+@pytest.mark.parametrize("kind,bc", [("constant", 0), ("rotation", 0),
+                                     ("streamfunction", 0), ("streamfunction", 1)])
+def test_constant_field_is_preserved_bitwise(orc, kind, bc):
+    """psi = 1 under discretely divergence-free Courant numbers (constant,
+    solid-body rotation, or a streamfunction quantised to 2**-16 so every
+    flux difference is exact) stays exactly 1, with variable h."""
+    shape = (8, 12, 16)
+    u1, u2, u3, h = _fields_for_constant(kind, shape, bc)
+    psi = np.ones(shape)
+    out = orc.run(psi, u1, u2, u3, h, 3, bc=bc)
+    np.testing.assert_array_equal(out, psi)
+
+
+# --------------------------------------------------------------- mass
+
+def test_mass_is_conserved_periodic(orc):
+    """Flux form + periodic faces: sum h*psi is unchanged up to the rounding
+    of the per-cell division by h (bound: ~10 n u (1 + sum|C|) sum|h psi|)."""
+    shape = (8, 12, 16)
+    f = inputs.random_smooth(21, shape, cmax=0.15)
+    m0 = orc.mass(f.psi, f.h)
+    nsteps = 10
+    out = orc.run(f.psi, f.u1, f.u2, f.u3, f.h, nsteps)
+    m1 = orc.mass(out, f.h)
+    bound = 10 * nsteps * U * (1 + 6 * 0.15) * np.abs(f.h * f.psi).sum()
+    assert abs(m1 - m0) <= bound
+    # and it is genuinely small, not just under a loose bound
+    assert abs(m1 - m0) / m0 < 1e-13
+
+
+def test_mass_budget_open_boundaries(orc):
+    """Open (zero-gradient) boundaries: the mass change of one step equals
+    the net inflow of the first-order fluxes through the domain faces (the
+    corrective fluxes vanish there)."""
+    shape = (6, 10, 14)
+    f = inputs.random_smooth(33, shape, bc=inputs.BC_OPEN, cmax=0.15)
+    m0 = orc.mass(f.psi, f.h)
+    out = orc.step(f.psi, f.u1, f.u2, f.u3, f.h, bc=inputs.BC_OPEN)
+    m1 = orc.mass(out, f.h)
+    inflow = orc.open_inflow(f.psi, f.u1, f.u2, f.u3)
+    assert abs(inflow) > 1e-3
+    assert abs((m1 - m0) - inflow) <= 1e-12 * np.abs(f.h * f.psi).sum()
+
+
+def test_mass_sum_is_exact_to_rounding(orc):
+    """Dot2 against the exact rational sum of h*psi on small arrays, including
+    cancelling signs: the error is within one rounding of the exact value
+    plus a term of order u^2 * sum|h psi|."""
+    rng = np.random.default_rng(3)
+    for trial in range(20):
+        n = int(rng.integers(1, 300))
+        h = rng.uniform(0.5, 1.5, n)
+        psi = rng.normal(size=n) * 10.0 ** rng.integers(-3, 4, n)
+        exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(h, psi))
+        got = orc.mass(psi, h)
+        err = abs(Fraction(got) - exact)
+        cond = sum(abs(Fraction(float(a)) * Fraction(float(b))) for a, b in zip(h, psi))
+        assert err <= Fraction(U) * abs(exact) + Fraction(4 * n * n) * Fraction(U) ** 2 * cond
+
+
+# ------------------------------------------------ positivity and monotonicity
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_positivity_and_no_new_extrema(orc, bc):
+    """Divergence-free flow with outflow <= h and the limiter on: psi stays
+    non-negative, the global max never grows and the global min never drops
+    (to rounding).  Uses a zero background with a sharp block, where the
+    unlimited scheme does overshoot."""
+    shape = (10, 16, 16)
+    f = inputs.random_smooth(41, shape, bc=bc, divergence_free=True, cmax=0.4, hvar=0.0)
+    psi = np.zeros(shape)
+    psi[3:7, 5:11, 4:12] = 1.0
+    lo, hi = psi.min(), psi.max()
+    cur = psi
+    for _ in range(12):
+        cur = orc.step(cur, f.u1, f.u2, f.u3, f.h, bc=bc, nonos=True)
+        assert cur.min() >= lo - 4 * U
+        assert cur.max() <= hi * (1 + 8 * U)
+    un = psi
+    for _ in range(12):
+        un = orc.step(un, f.u1, f.u2, f.u3, f.h, bc=bc, nonos=False)
+    assert un.max() > hi + 1e-3 or un.min() < lo - 1e-3
+
+
+# ------------------------------------------------------- order of accuracy
+
+def _order_1d(orc, iord, hvar, sizes=(64, 128, 256), C=0.4):
+    """Max error against the exact solution of d(h psi)/dt + d(C psi)/dx = 0:
+    psi is constant along dx/dt = C/h(x), i.e. int_{X0}^{x} h = C t."""
+    errs = []
+    for N in sizes:
+        x = np.arange(N) + 0.5
+        psi0 = 2 + np.sin(2 * np.pi * x / N)
+        steps = int(round(N / 4 / C))
+        h = 1 + hvar * np.sin(2 * np.pi * x / N)
+        H = lambda s: s - hvar * N / (2 * np.pi) * np.cos(2 * np.pi * s / N)
+        X0 = x - C * steps
+        for _ in range(60):
+            X0 = X0 + (H(x) - H(X0) - C * steps) / (1 + hvar * np.sin(2 * np.pi * X0 / N))
+        exact = 2 + np.sin(2 * np.pi * X0 / N)
+        out = orc.run(psi0.reshape(1, 1, N), np.full((1, 1, N + 1), C), np.zeros((1, 2, N)),
+                      np.zeros((2, 1, N)), h.reshape(1, 1, N), steps, iord=iord, nonos=False)
+        errs.append(np.abs(out.ravel() - exact).max())
+    return [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+
+
+@pytest.mark.parametrize("hvar", [0.0, 0.3])
+def test_donor_cell_is_first_order(orc, hvar):
+    for r in _order_1d(orc, 1, hvar):
+        assert 1.85 < r < 2.15
+
+
+@pytest.mark.parametrize("hvar", [0.0, 0.3])
+def test_mpdata_is_second_order_1d(orc, hvar):
+    """One corrective pass makes the scheme second order; with variable h
+    this holds only with the face density G in the pseudo-velocity."""
+    for r in _order_1d(orc, 2, hvar):
+        assert 3.7 < r < 4.4
+
+
+@pytest.mark.parametrize("c", [(0.3, 0.2, 0.0), (0.2, -0.15, 0.1)])
+def test_mpdata_is_second_order_oblique(orc, c):
+    """Oblique constant flow: second order requires the cross-derivative
+    terms (B2, B3 with the averaged transverse Courant numbers)."""
+    errs = []
+    for N in (16, 32, 64):
+        nz = N if c[2] != 0.0 else 1
+        zc, yc, xc = [np.arange(n) + 0.5 for n in (nz, N, N)]
+        Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+        prof = lambda X, Y, Z: (2 + np.sin(2 * np.pi * X / N) * np.cos(2 * np.pi * Y / N)
+                                * (np.cos(2 * np.pi * Z / nz) if nz > 1 else 1.0))
+        steps = int(round(N / 4 / 0.4))
+        u1, u2, u3 = inputs.constant_courant((nz, N, N), c)
+        out = orc.run(prof(X, Y, Z), u1, u2, u3, np.ones((nz, N, N)), steps, nonos=False)
+        exact = prof(X - c[0] * steps, Y - c[1] * steps, Z - c[2] * steps)
+        errs.append(np.abs(out - exact).max())
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert ratios[-1] > 3.6, ratios
+
+
+# ------------------------------------------------------------- symmetries
+
+def test_translation_equivariance_bitwise(orc):
+    """Constant Courant numbers, periodic grid: rolling the input rolls the
+    output, bit for bit (every cell runs the same operations)."""
+    shape = (6, 9, 11)
+    rng = np.random.default_rng(5)
+    psi = rng.uniform(0.2, 1.0, shape)
+    u1, u2, u3 = inputs.constant_courant(shape, (0.3, -0.2, 0.15))
+    h = np.ones(shape)
+    a = orc.step(psi, u1, u2, u3, h)
+    sh = (2, -3, 4)
+    b = orc.step(np.roll(psi, sh, axis=(0, 1, 2)), u1, u2, u3, h)
+    np.testing.assert_array_equal(np.roll(a, sh, axis=(0, 1, 2)), b)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_mirror_symmetry(orc, bc):
+    """Reflecting x (reverse the cells, reverse and negate the x-faces) maps
+    the solution onto its reflection, to rounding."""
+    f = inputs.random_smooth(51, (6, 8, 10), bc=bc, cmax=0.15)
+    a = orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 3, bc=bc)
+    b = orc.run(f.psi[:, :, ::-1], -f.u1[:, :, ::-1], f.u2[:, :, ::-1], f.u3[:, :, ::-1],
+                f.h[:, :, ::-1], 3, bc=bc)
+    np.testing.assert_allclose(b[:, :, ::-1], a, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_axis_permutation_symmetry(orc, bc):
+    """Swapping x and y (transpose the arrays, exchange u1 and u2) maps the
+    solution onto its transpose, to rounding."""
+    f = inputs.random_smooth(61, (5, 9, 7), bc=bc, cmax=0.15)
+    a = orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 3, bc=bc)
+    t = lambda x: np.ascontiguousarray(np.swapaxes(x, 1, 2))
+    b = orc.run(t(f.psi), t(f.u2), t(f.u1), t(f.u3), t(f.h), 3, bc=bc)
+    np.testing.assert_allclose(t(b), a, rtol=0, atol=1e-13)
+
+
+def test_cyclic_axis_permutation_symmetry(orc):
+    """x -> y -> z -> x: the pseudo-velocity is written once and applied by
+    cyclic permutation, so rotating the axes of the problem rotates the
+    answer (to rounding)."""
+    f = inputs.random_smooth(71, (6, 7, 8), cmax=0.15)
+    a = orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 2)
+    # new axes (z', y', x') = (y, x, z): array axes (0,1,2) -> (1,2,0)
+    r = lambda x: np.ascontiguousarray(np.transpose(x, (1, 2, 0)))
+    b = orc.run(r(f.psi), r(f.u3), r(f.u1), r(f.u2), r(f.h), 2)
+    np.testing.assert_allclose(b, r(a), rtol=0, atol=1e-13)
+
+
+# ----------------------------------------------------------- small details
+
+def test_iord_one_is_the_first_pass(orc):
+    f = inputs.random_smooth(81, (4, 5, 6), cmax=0.15)
+    out, st = orc.step(f.psi, f.u1, f.u2, f.u3, f.h, iord=2, stages=True)
+    out1 = orc.step(f.psi, f.u1, f.u2, f.u3, f.h, iord=1)
+    np.testing.assert_array_equal(out1, st["psi1"])
+
+
+def test_bounds_are_the_7_point_extrema(orc):
+    """The limiter bounds against a brute-force loop over the 7-point
+    neighbourhood of both fields (the paper's stage 8, Listing 1)."""
+    f = inputs.random_smooth(91, (4, 5, 6), cmax=0.15)
+    _, st = orc.step(f.psi, f.u1, f.u2, f.u3, f.h, stages=True)
+    p1 = st["psi1"]
+    nz, ny, nx = f.psi.shape
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                vals = []
+                for dk, dj, di in [(0, 0, 0), (0, 0, -1), (0, 0, 1), (0, -1, 0), (0, 1, 0),
+                                   (-1, 0, 0), (1, 0, 0)]:
+                    kk, jj, ii = (k + dk) % nz, (j + dj) % ny, (i + di) % nx
+                    vals += [f.psi[kk, jj, ii], p1[kk, jj, ii]]
+                assert st["mx"][k, j, i] == max(vals)
+                assert st["mn"][k, j, i] == min(vals)
+
+
+def test_parameter_validation(orc):
+    f = inputs.random_smooth(1, (2, 3, 4))
+    with pytest.raises(ValueError):
+        orc.step(f.psi, f.u1, f.u2, f.u3, f.h, iord=3)
+    with pytest.raises(ValueError):
+        orc.step(f.psi, f.u1, f.u2, f.u3, f.h, bc=2)
+    with pytest.raises(ValueError):
+        orc.step(f.psi, f.u1[:, :, :-1], f.u2, f.u3, f.h)
