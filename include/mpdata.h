@@ -1,0 +1,140 @@
+/*
+ * mpdata.h -- C ABI of libmpdata, an MI355X (gfx950) implementation of the
+ * MPDATA advection time step.
+ *
+ * The operation.  One MPDATA time step advances a cell-centred scalar psi
+ * through a chain of dependent stencil stages that read five input matrices
+ * (psi, the three face Courant numbers u1, u2, u3, and the density h) and
+ * produce one output matrix, psi at the next time level (paper, section 5.2,
+ * "Introduction to MPDATA"; the 7-point neighbourhood maximum of Listing 1
+ * is one of the stages).  The stages are the donor-cell (upwind) pass, the
+ * antidiffusive pseudo-velocities, the non-oscillatory limiter (bounds,
+ * factors, limited velocities) and the corrective donor-cell pass, as
+ * defined in the MPDATA literature the paper cites (Smolarkiewicz 1984;
+ * Smolarkiewicz & Grabowski 1990; the density-weighted form of Smolarkiewicz
+ * & Margolin 1998).  The library fuses all stages of a step into one
+ * kernel, so intermediates never leave the chip (the paper's (3+1)D
+ * decomposition idea, section 5.3, recast for LDS and registers).
+ *
+ * Conventions shared by every entry point.
+ *  - All functions are thread-compatible, never abort and never throw;
+ *    they return MPDATA_OK (0) or a negative error code.  The text of the
+ *    last error of a context is returned by mpdata_last_error().
+ *  - Grid: nx * ny * nz cells, C order [k][j][i] with i (x) fastest.
+ *  - Face Courant arrays hold n+1 faces along their own axis:
+ *      u1[nz][ny][nx+1]   face i' lies between cells i'-1 and i'
+ *      u2[nz][ny+1][nx]
+ *      u3[nz+1][ny][nx]
+ *    A positive value carries mass toward +axis.  With periodic boundaries
+ *    face n along an axis is the same face as face 0 and must hold the
+ *    same value (checked by mpdata_create).
+ *  - Element type: double for MPDATA_FP64; float for MPDATA_FP32, which
+ *    stores fields and runs the bulk stencil in FP32 while the limiter's
+ *    inflow/outflow sums, its divides and its min() run in FP64 and mass
+ *    sums are compensated (double-double).
+ *  - Pointers named "device" are device memory of the current HIP device;
+ *    the caller owns them and keeps them alive until mpdata_destroy().  The
+ *    library allocates no device memory: everything it needs beyond the
+ *    caller's arrays lives in the caller's workspace.
+ *  - Work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *    void*, NULL = the legacy default stream) and is asynchronous unless
+ *    stated otherwise.
+ */
+#ifndef MPDATA_H
+#define MPDATA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPDATA_ABI_VERSION 1
+
+enum {
+    MPDATA_OK = 0,
+    MPDATA_EINVAL = -1,     /* invalid argument (message says which) */
+    MPDATA_ENOMEM = -2,     /* workspace too small / host allocation failed */
+    MPDATA_EDEVICE = -3,    /* a HIP call failed (message holds its text) */
+    MPDATA_ENOTSUP = -4,    /* valid but unsupported combination */
+    MPDATA_ENONFINITE = -5  /* a mass sum found NaN or Inf in psi */
+};
+
+enum { MPDATA_FP64 = 0, MPDATA_FP32 = 1 };
+enum { MPDATA_BC_PERIODIC = 0, MPDATA_BC_OPEN = 1 }; /* OPEN = zero gradient */
+
+typedef struct {
+    int32_t nx, ny, nz;   /* cells, each >= 1 */
+    int32_t dtype;        /* MPDATA_FP64 or MPDATA_FP32 */
+    int32_t bc;           /* MPDATA_BC_PERIODIC or MPDATA_BC_OPEN (all axes) */
+    int32_t iord;         /* 1: donor cell only; 2: one corrective pass */
+    int32_t nonos;        /* 1: non-oscillatory limiter on (needs iord 2) */
+    int32_t tile;         /* launch shape: 0 = library default, else an id
+                             from mpdata_tile_count()/mpdata_tile_info() */
+    double eps;           /* > 0, regularises the ratio denominators of the
+                             pseudo-velocity and of the limiter; 1e-15 is the
+                             usual value */
+} mpdata_params;
+
+typedef struct mpdata_ctx mpdata_ctx; /* opaque */
+
+/* Bytes of workspace mpdata_create() needs for these parameters (0 if they
+ * are invalid).  The workspace holds the second psi buffer of the time loop
+ * and the mass-reduction partials. */
+size_t mpdata_workspace_bytes(const mpdata_params *p);
+
+/* Validates the parameters and arrays and binds them to a new context.
+ *   psi        device, read-write, nx*ny*nz elements: the state, updated in
+ *              place by mpdata_step()
+ *   u1,u2,u3,h device, read-only for the lifetime of the context
+ *   workspace  device, >= mpdata_workspace_bytes(p) bytes, 256-byte aligned
+ *   stream     hipStream_t of the caller (NULL = default stream)
+ * Checks: dims >= 1, enum ranges, eps > 0, non-NULL 16-byte-aligned
+ * pointers, h > 0 everywhere, and (periodic) face n == face 0 bit for bit
+ * on every axis.  These checks read the arrays and synchronise the stream.
+ * On success *out receives the context; on failure *out is set to NULL. */
+int mpdata_create(const mpdata_params *p, void *psi, const void *u1, const void *u2,
+                  const void *u3, const void *h, void *workspace, size_t ws_bytes,
+                  void *stream, mpdata_ctx **out);
+
+/* Enqueues nsteps >= 0 time steps.  On return of the enqueued work psi holds
+ * the state after the steps (an odd step count ends with one device copy
+ * from the workspace into psi). */
+int mpdata_step(mpdata_ctx *ctx, int32_t nsteps);
+
+/* Mass M = sum over cells of h*psi with a compensated (double-double)
+ * reduction: wave-level and block-level partials, then one deterministic
+ * final pass.  Synchronises the stream; MPDATA_ENONFINITE if psi holds a
+ * NaN or Inf. */
+int mpdata_mass(mpdata_ctx *ctx, double *out);
+
+/* Device-to-device copies of the state (asynchronous on the stream). */
+int mpdata_get_psi(mpdata_ctx *ctx, void *dst_device);
+int mpdata_set_psi(mpdata_ctx *ctx, const void *src_device);
+
+/* Waits for all work enqueued by this context. */
+int mpdata_sync(mpdata_ctx *ctx);
+
+/* Number of time steps executed since creation (or the last set_psi). */
+int64_t mpdata_steps_done(const mpdata_ctx *ctx);
+
+/* Releases the context (NULL-safe).  Never frees caller memory. */
+void mpdata_destroy(mpdata_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none); with ctx == NULL the
+ * message of the last failed mpdata_create() on this thread. */
+const char *mpdata_last_error(const mpdata_ctx *ctx);
+
+/* Launch shapes of the fused step kernel.  Shape id 1..count; for each the
+ * x-y output tile (tx, ty) and the threads per workgroup. */
+int mpdata_tile_count(void);
+int mpdata_tile_info(int32_t id, int32_t *tx, int32_t *ty, int32_t *threads);
+
+/* Version of this ABI (MPDATA_ABI_VERSION). */
+int mpdata_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPDATA_H */

@@ -1,0 +1,161 @@
+"""ctypes binding of libmpdata (include/mpdata.h): argument marshalling only.
+
+Every function here forwards to the C entry point of the same name; all
+arithmetic runs in the library's HIP kernels.  The library must have been
+built (``python -m paper_1507_01265_amd.build``); if it is missing, loading
+fails loudly -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpdata.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mpdata.h")
+
+MPDATA_OK = 0
+MPDATA_EINVAL = -1
+MPDATA_ENOMEM = -2
+MPDATA_EDEVICE = -3
+MPDATA_ENOTSUP = -4
+MPDATA_ENONFINITE = -5
+MPDATA_FP64 = 0
+MPDATA_FP32 = 1
+MPDATA_BC_PERIODIC = 0
+MPDATA_BC_OPEN = 1
+
+ERRORS = {MPDATA_EINVAL: "EINVAL", MPDATA_ENOMEM: "ENOMEM", MPDATA_EDEVICE: "EDEVICE",
+          MPDATA_ENOTSUP: "ENOTSUP", MPDATA_ENONFINITE: "ENONFINITE"}
+
+
+class mpdata_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("bc", ctypes.c_int32), ("iord", ctypes.c_int32),
+                ("nonos", ctypes.c_int32), ("tile", ctypes.c_int32), ("eps", ctypes.c_double)]
+
+
+class MpdataError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {message}")
+        self.code = code
+
+
+_lib = None
+
+_SIGNATURES = {
+    "mpdata_abi_version": ([], ctypes.c_int),
+    "mpdata_tile_count": ([], ctypes.c_int),
+    "mpdata_tile_info": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+                         ctypes.c_int),
+    "mpdata_workspace_bytes": ([ctypes.POINTER(mpdata_params)], ctypes.c_size_t),
+    "mpdata_create": ([ctypes.POINTER(mpdata_params), ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+                      ctypes.c_int),
+    "mpdata_step": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int),
+    "mpdata_mass": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "mpdata_get_psi": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "mpdata_set_psi": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "mpdata_sync": ([ctypes.c_void_p], ctypes.c_int),
+    "mpdata_steps_done": ([ctypes.c_void_p], ctypes.c_int64),
+    "mpdata_destroy": ([ctypes.c_void_p], None),
+    "mpdata_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
+}
+
+
+def load():
+    """Load libmpdata.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1507_01265_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def hip_runtimes_mapped():
+    """Paths of every libamdhip64 mapped into this process (the library must
+    share torch's HIP runtime, so exactly one is expected once torch is
+    imported)."""
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64" in line:
+                paths.add(line.split()[-1])
+    return sorted(paths)
+
+
+def check(code: int, ctx=None):
+    if code != MPDATA_OK:
+        msg = load().mpdata_last_error(ctx).decode(errors="replace")
+        raise MpdataError(code, msg)
+
+
+# ------------------------------------------------ thin wrappers, same names
+
+def mpdata_abi_version() -> int:
+    return load().mpdata_abi_version()
+
+
+def mpdata_tile_count() -> int:
+    return load().mpdata_tile_count()
+
+
+def mpdata_tile_info(tile_id: int):
+    tx, ty, th = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(load().mpdata_tile_info(tile_id, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(th)))
+    return tx.value, ty.value, th.value
+
+
+def mpdata_workspace_bytes(params: mpdata_params) -> int:
+    return int(load().mpdata_workspace_bytes(ctypes.byref(params)))
+
+
+def mpdata_create(params, psi, u1, u2, u3, h, workspace, ws_bytes, stream):
+    out = ctypes.c_void_p()
+    code = load().mpdata_create(ctypes.byref(params), psi, u1, u2, u3, h, workspace, ws_bytes,
+                                stream, ctypes.byref(out))
+    check(code, None)
+    return out.value
+
+
+def mpdata_step(ctx, nsteps: int):
+    check(load().mpdata_step(ctx, nsteps), ctx)
+
+
+def mpdata_mass(ctx) -> float:
+    out = ctypes.c_double()
+    check(load().mpdata_mass(ctx, ctypes.byref(out)), ctx)
+    return out.value
+
+
+def mpdata_get_psi(ctx, dst):
+    check(load().mpdata_get_psi(ctx, dst), ctx)
+
+
+def mpdata_set_psi(ctx, src):
+    check(load().mpdata_set_psi(ctx, src), ctx)
+
+
+def mpdata_sync(ctx):
+    check(load().mpdata_sync(ctx), ctx)
+
+
+def mpdata_steps_done(ctx) -> int:
+    return int(load().mpdata_steps_done(ctx))
+
+
+def mpdata_destroy(ctx):
+    load().mpdata_destroy(ctx)
+
+
+def mpdata_last_error(ctx=None) -> str:
+    return load().mpdata_last_error(ctx).decode(errors="replace")

@@ -1,0 +1,83 @@
+"""Host-side checks of libmpdata that need no GPU: the library loads, exports
+every entry point include/mpdata.h declares, and rejects invalid arguments
+before touching the device."""
+import ctypes
+import re
+
+import pytest
+
+from paper_1507_01265_amd import _lib
+
+
+def _declared():
+    src = open(_lib.HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpdata_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_core_entry_points():
+    names = _declared()
+    for core in ("mpdata_create", "mpdata_step", "mpdata_destroy", "mpdata_mass",
+                 "mpdata_workspace_bytes"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(_declared()) <= set(_lib._SIGNATURES)
+
+
+def test_abi_version_and_tiles():
+    assert _lib.mpdata_abi_version() == 1
+    n = _lib.mpdata_tile_count()
+    assert n >= 1
+    for t in range(1, n + 1):
+        tx, ty, threads = _lib.mpdata_tile_info(t)
+        assert tx >= 1 and ty >= 1 and 64 <= threads <= 1024
+    with pytest.raises(_lib.MpdataError):
+        _lib.mpdata_tile_info(n + 1)
+
+
+def _params(**kw):
+    d = dict(nx=32, ny=32, nz=16, dtype=0, bc=0, iord=2, nonos=1, tile=0, eps=1e-15)
+    d.update(kw)
+    return _lib.mpdata_params(**d)
+
+
+def test_workspace_bytes():
+    b64 = _lib.mpdata_workspace_bytes(_params())
+    b32 = _lib.mpdata_workspace_bytes(_params(dtype=1))
+    assert b64 >= 32 * 32 * 16 * 8 and b32 >= 32 * 32 * 16 * 4 and b64 > b32
+    assert b64 % 256 == 0
+
+
+@pytest.mark.parametrize("bad", [dict(nx=0), dict(nz=-1), dict(dtype=2), dict(bc=5),
+                                 dict(iord=3), dict(iord=1, nonos=1), dict(nonos=2),
+                                 dict(eps=0.0), dict(eps=float("nan")), dict(tile=99),
+                                 dict(nx=4096, ny=4096, nz=256)])
+def test_invalid_params_are_rejected(bad):
+    p = _params(**bad)
+    assert _lib.mpdata_workspace_bytes(p) == 0
+    with pytest.raises(_lib.MpdataError) as e:
+        _lib.mpdata_create(p, 256, 256, 256, 256, 256, 256, 1 << 30, None)
+    assert e.value.code == _lib.MPDATA_EINVAL
+    assert _lib.mpdata_last_error(None)
+
+
+def test_null_and_misaligned_pointers_are_rejected():
+    p = _params()
+    with pytest.raises(_lib.MpdataError, match="NULL"):
+        _lib.mpdata_create(p, None, 256, 256, 256, 256, 256, 1 << 30, None)
+    with pytest.raises(_lib.MpdataError, match="aligned"):
+        _lib.mpdata_create(p, 258, 256, 256, 256, 256, 256, 1 << 30, None)
+    with pytest.raises(_lib.MpdataError, match="workspace"):
+        _lib.mpdata_create(p, 256, 256, 256, 256, 256, 256, 16, None)
+
+
+def test_destroy_is_null_safe():
+    _lib.mpdata_destroy(None)

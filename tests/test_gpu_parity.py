@@ -1,0 +1,257 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+FP64 bar: relative max-norm error <= 1e-12 (max|gpu - oracle| / max|oracle|).
+FP32 bar (FP32 storage and bulk arithmetic, FP64 limiter): the FP64 oracle
+runs on the same FP32-rounded inputs; per step the FP32 path commits a few
+units of FP32 rounding (2^-24 ~ 6e-8) per stage, so after n steps we allow
+rel-Linf <= 2e-6 * n and rel-L2 <= 5e-7 * n.
+"""
+import numpy as np
+import pytest
+
+from paper_1507_01265_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1507_01265_amd import _lib
+    _lib.load()
+
+
+def _solver(fields, dtype=torch.float64, **kw):
+    from paper_1507_01265_amd.solver import Solver
+    return Solver.from_numpy(fields, dtype=dtype, **kw)
+
+
+def gpu_run(fields, steps, dtype=torch.float64, **kw):
+    s = _solver(fields, dtype=dtype, **kw)
+    s.step(steps)
+    s.sync()
+    out = s.psi.cpu().numpy().astype(np.float64)
+    s.close()
+    return out
+
+
+def rel_linf(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def oracle_run(orc, f, steps, **kw):
+    return orc.run(f.psi, f.u1, f.u2, f.u3, f.h, steps, bc=f.bc, **kw)
+
+
+# ------------------------------------------------------------------ FP64
+
+def test_parity_small_config(orc):
+    """32x32x16 periodic, constant Courant (0.3,0.2,0.1), 10 steps, limiter on."""
+    f = inputs.parity_small()
+    want = oracle_run(orc, f, 10)
+    got = gpu_run(f, 10)
+    err = rel_linf(got, want)
+    print(f"parity_small rel-Linf {err:.3e} max|diff| {np.abs(got - want).max():.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["periodic", "open"])
+@pytest.mark.parametrize("nonos", [True, False], ids=["nonos", "unlimited"])
+def test_parity_every_tile_ragged(orc, bc, nonos):
+    """70x45x13 (several tiles and ragged tails on every axis), variable h,
+    random face Courant numbers: every launch shape matches the oracle and
+    all shapes agree bit for bit."""
+    from paper_1507_01265_amd import _lib
+    f = inputs.random_smooth(101, (13, 45, 70), bc=bc, cmax=0.15)
+    want = oracle_run(orc, f, 4, nonos=nonos)
+    first = None
+    for tile in range(1, _lib.mpdata_tile_count() + 1):
+        print(f"tile {tile} bc {bc} nonos {nonos}", flush=True)
+        got = gpu_run(f, 4, nonos=nonos, tile=tile)
+        assert rel_linf(got, want) <= 1e-12, (tile, rel_linf(got, want))
+        if first is None:
+            first = got
+        else:
+            np.testing.assert_array_equal(got, first)
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["periodic", "open"])
+def test_parity_divergence_free_with_zero_background(orc, bc):
+    """Streamfunction flow on a zero background with a sharp block: exercises
+    A = 0/eps, the limiter at zero bounds and the open-boundary budget."""
+    f = inputs.random_smooth(103, (10, 40, 66), bc=bc, divergence_free=True, cmax=0.45)
+    psi = np.zeros_like(f.psi)
+    psi[2:8, 10:30, 20:50] = 1.0
+    f.psi = psi
+    want = oracle_run(orc, f, 6)
+    got = gpu_run(f, 6)
+    assert rel_linf(got, want) <= 1e-12
+    assert got.min() >= -1e-15
+
+
+def test_parity_donor_cell_only(orc):
+    f = inputs.random_smooth(105, (9, 21, 37), cmax=0.15)
+    for bc in (0, 1):
+        f.bc = bc
+        want = oracle_run(orc, f, 3, iord=1, nonos=False)
+        got = gpu_run(f, 3, iord=1, nonos=False)
+        assert rel_linf(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 9), (7, 1, 1), (1, 6, 1), (2, 5, 3),
+                                   (3, 1, 66), (1, 17, 2), (5, 3, 61)])
+@pytest.mark.parametrize("bc", [0, 1], ids=["periodic", "open"])
+def test_degenerate_shapes(orc, shape, bc):
+    f = inputs.random_smooth(107, shape, bc=bc, cmax=0.15)
+    want = oracle_run(orc, f, 3)
+    got = gpu_run(f, 3)
+    assert rel_linf(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("steps", [0, 1, 3])
+def test_step_counts(orc, steps):
+    """Odd counts end with a copy from the workspace; 0 is a no-op."""
+    f = inputs.random_smooth(109, (6, 12, 20), cmax=0.15)
+    want = oracle_run(orc, f, steps)
+    got = gpu_run(f, steps)
+    assert rel_linf(got, want) <= 1e-12
+
+
+def test_courant_one_shift_is_exact():
+    f = inputs.random_smooth(111, (5, 9, 13))
+    f.psi = 1.0 + np.random.default_rng(1).uniform(0, 1, f.psi.shape) * 0.999
+    f.u1, f.u2, f.u3 = inputs.constant_courant(f.psi.shape, (1.0, 0.0, 0.0))
+    f.h = np.ones_like(f.psi)
+    got = gpu_run(f, 1)
+    np.testing.assert_array_equal(got, np.roll(f.psi, 1, axis=2))
+
+
+def test_constant_field_preserved():
+    f = inputs.random_smooth(113, (8, 30, 40), divergence_free=True, cmax=0.45)
+    f.psi = np.ones_like(f.psi)
+    got = gpu_run(f, 5)
+    np.testing.assert_array_equal(got, f.psi)
+
+
+# ------------------------------------------------------------------ mass
+
+def test_mass_matches_oracle(orc):
+    f = inputs.random_smooth(115, (16, 40, 72), cmax=0.15)
+    s = _solver(f)
+    m0 = s.mass()
+    assert abs(m0 - orc.mass(f.psi, f.h)) <= 2e-16 * abs(m0)
+    s.step(6)
+    m1 = s.mass()
+    want = orc.mass(s.psi.cpu().numpy(), f.h)
+    assert abs(m1 - want) <= 2e-16 * abs(want)
+    assert abs(m1 - m0) <= 1e-13 * abs(m0)       # periodic: conserved
+    s.close()
+
+
+def test_mass_fp32_is_compensated(orc):
+    f = inputs.random_smooth(117, (16, 40, 72), cmax=0.15).astype(np.float32)
+    s = _solver(f, dtype=torch.float32)
+    m = s.mass()
+    want = orc.mass(f.psi.astype(np.float64), f.h.astype(np.float64))
+    assert abs(m - want) <= 2e-16 * abs(want)
+    s.close()
+
+
+def test_mass_reports_nonfinite():
+    from paper_1507_01265_amd import _lib
+    f = inputs.random_smooth(119, (4, 8, 8))
+    f.psi[1, 2, 3] = np.nan
+    s = _solver(f)
+    with pytest.raises(_lib.MpdataError) as e:
+        s.mass()
+    assert e.value.code == _lib.MPDATA_ENONFINITE
+    s.close()
+
+
+# ------------------------------------------------------------ validation
+
+def test_create_rejects_mismatched_periodic_faces():
+    from paper_1507_01265_amd import _lib
+    f = inputs.random_smooth(121, (4, 8, 8))
+    f.u2[2, -1, 3] += 0.01
+    with pytest.raises(_lib.MpdataError, match="face"):
+        _solver(f)
+
+
+def test_create_rejects_nonpositive_density():
+    from paper_1507_01265_amd import _lib
+    f = inputs.random_smooth(123, (4, 8, 8))
+    f.h[0, 0, 0] = 0.0
+    with pytest.raises(_lib.MpdataError, match="h must"):
+        _solver(f)
+
+
+# ------------------------------------------------ determinism and restart
+
+def test_deterministic_and_restartable():
+    f = inputs.random_smooth(125, (12, 33, 47), cmax=0.15)
+    a = gpu_run(f, 10)
+    b = gpu_run(f, 10)
+    np.testing.assert_array_equal(a, b)
+    s = _solver(f)
+    s.step(5)
+    saved = torch.empty_like(s.psi)
+    s.get_psi(saved)
+    s.step(3)                       # diverge, then restore
+    s.set_psi(saved)
+    s.step(5)
+    s.sync()
+    np.testing.assert_array_equal(s.psi.cpu().numpy(), a)
+    s.close()
+
+
+# ------------------------------------------------------------------ FP32
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["periodic", "open"])
+def test_fp32_against_fp64_oracle(orc, bc):
+    steps = 8
+    f = inputs.random_smooth(127, (12, 50, 70), bc=bc, cmax=0.15).astype(np.float32)
+    want = oracle_run(orc, f.as_f64(), steps)
+    got = gpu_run(f, steps, dtype=torch.float32)
+    e_inf, e_2 = rel_linf(got, want), rel_l2(got, want)
+    print(f"fp32 bc={bc} rel-Linf {e_inf:.3e} rel-L2 {e_2:.3e}")
+    assert e_inf <= 2e-6 * steps and e_2 <= 5e-7 * steps
+
+
+def test_fp32_every_tile_agrees(orc):
+    from paper_1507_01265_amd import _lib
+    f = inputs.random_smooth(129, (7, 45, 70), cmax=0.15).astype(np.float32)
+    first = None
+    for tile in range(1, _lib.mpdata_tile_count() + 1):
+        got = gpu_run(f, 3, dtype=torch.float32, tile=tile)
+        if first is None:
+            first = got
+        np.testing.assert_array_equal(got, first)
+
+
+# ------------------------------------------------------------ full sizes
+
+@pytest.mark.slow
+def test_full_size_rotation_fp64(orc):
+    """512x256x64, the rotation workload at full size, 2 steps."""
+    f = inputs.rotation()
+    want = oracle_run(orc, f, 2)
+    got = gpu_run(f, 2)
+    assert rel_linf(got, want) <= 1e-12
+    assert got.min() >= -1e-15
+
+
+@pytest.mark.slow
+def test_full_size_streamfunction_fp32(orc):
+    """1024x512x64 open domain, FP32 + FP64 limiter, 1 step at full size."""
+    f = inputs.streamfunction().astype(np.float32)
+    want = oracle_run(orc, f.as_f64(), 1)
+    got = gpu_run(f, 1, dtype=torch.float32)
+    assert rel_linf(got, want) <= 2e-6 and rel_l2(got, want) <= 5e-7
