@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="launch shape id (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-MiB device buffer once (a copy kernel of "
+                         "known size for scaling HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -163,6 +166,14 @@ def main():
                                 "cores": oracle.threads(), "kind": "oracle",
                                 "sample": f"{nx}x{ny}x{nz} {args.workload} inputs, {steps} FP64 "
                                           f"steps of the whole grid, {el:.1f} s"}
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = 2 * n * 8
     print(json.dumps(line), flush=True)
 
 

@@ -62,6 +62,9 @@ enum {
 };
 
 enum { MPDATA_FP64 = 0, MPDATA_FP32 = 1 };
+/* flags: launch every step on its own instead of replaying a captured
+ * graph of step launches */
+enum { MPDATA_FLAG_NO_GRAPH = 1 };
 enum { MPDATA_BC_PERIODIC = 0, MPDATA_BC_OPEN = 1 }; /* OPEN = zero gradient */
 
 typedef struct {
@@ -72,6 +75,8 @@ typedef struct {
     int32_t nonos;        /* 1: non-oscillatory limiter on (needs iord 2) */
     int32_t tile;         /* launch shape: 0 = library default, else an id
                              from mpdata_tile_count()/mpdata_tile_info() */
+    int32_t flags;        /* MPDATA_FLAG_* bits, 0 = defaults */
+    int32_t reserved;     /* must be 0 */
     double eps;           /* > 0, regularises the ratio denominators of the
                              pseudo-velocity and of the limiter; 1e-15 is the
                              usual value */
@@ -100,7 +105,9 @@ int mpdata_create(const mpdata_params *p, void *psi, const void *u1, const void 
 
 /* Enqueues nsteps >= 0 time steps.  On return of the enqueued work psi holds
  * the state after the steps (an odd step count ends with one device copy
- * from the workspace into psi). */
+ * from the workspace into psi).  Each step is one launch of the persistent
+ * fused kernel over a plan of (tile, z-range) segments balanced across the
+ * GPU; runs of steps are replayed from a hipGraph built on first use. */
 int mpdata_step(mpdata_ctx *ctx, int32_t nsteps);
 
 /* Mass M = sum over cells of h*psi with a compensated (double-double)
@@ -130,6 +137,67 @@ const char *mpdata_last_error(const mpdata_ctx *ctx);
  * x-y output tile (tx, ty) and the threads per workgroup. */
 int mpdata_tile_count(void);
 int mpdata_tile_info(int32_t id, int32_t *tx, int32_t *ty, int32_t *threads);
+
+/* Resident workgroups of the step kernel for (dtype, tile, bc, nonos) on the
+ * current device: *per_cu per compute unit, *cus compute units. */
+int mpdata_occupancy(int32_t dtype, int32_t tile, int32_t bc, int32_t nonos, int32_t *per_cu,
+                     int32_t *cus);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent grids of uneven sizes advanced together: every step is
+ * ONE launch of the persistent kernel whose workgroups walk a plan of
+ * segments (grid, tile_x, tile_y, z0, z1) -- the x-y output tile
+ * (tile_x, tile_y) of that grid over planes [z0, z1).  All grids of a batch
+ * share dtype, bc, iord (must be 2), nonos and eps; their sizes differ.  The
+ * plan decides which workgroup runs which segment (the per-CU assignment of
+ * uneven blocks); it can come from the library (plan == NULL: an even split
+ * of the work in planes) or from a caller-side tuner. */
+typedef struct mpdata_batch mpdata_batch; /* opaque */
+
+typedef struct {
+    int32_t tile;            /* launch shape id, 1..mpdata_tile_count() */
+    int32_t nwg;             /* workgroups of the persistent launch, >= 1 */
+    int32_t nseg;            /* number of segments */
+    int32_t reserved;        /* must be 0 */
+    const int32_t *seg;      /* host, nseg x 5 int32: grid, tile_x, tile_y, z0, z1 */
+    const int32_t *wg_begin; /* host, nwg + 1 int32: workgroup w runs segments
+                                [wg_begin[w], wg_begin[w+1]) in order */
+} mpdata_plan;
+
+/* Workspace bytes for a batch of n grids whose plans hold at most
+ * max_segments segments and max_wg workgroups (0 if the params are invalid
+ * or not batchable). */
+size_t mpdata_batch_workspace_bytes(int32_t n, const mpdata_params *params, int32_t max_segments,
+                                    int32_t max_wg);
+
+/* Segments and workgroups of the library's default plan for these grids and
+ * launch shape (tile 0 = default shape) on the current device. */
+int mpdata_batch_default_plan_size(int32_t n, const mpdata_params *params, int32_t tile,
+                                   int32_t *nseg, int32_t *nwg);
+
+/* Binds n >= 1 grids (params[i] and the device arrays psi[i], u1[i], u2[i],
+ * u3[i], h[i], as for mpdata_create) and a plan (NULL = default).  A plan is
+ * checked: every output tile of every grid covered exactly once over all
+ * planes.  Synchronises the stream. */
+int mpdata_batch_create(int32_t n, const mpdata_params *params, void *const *psi,
+                        const void *const *u1, const void *const *u2, const void *const *u3,
+                        const void *const *h, void *workspace, size_t ws_bytes, void *stream,
+                        const mpdata_plan *plan, mpdata_batch **out);
+
+/* nsteps >= 0 steps of every grid (asynchronous). */
+int mpdata_batch_step(mpdata_batch *b, int32_t nsteps);
+
+/* One step of every grid with the duration of each segment recorded:
+ * cycles_out[s] receives the wall-clock ticks (100 MHz) segment s of the plan
+ * took while all workgroups ran together.  Synchronises the stream. */
+int mpdata_batch_profile_step(mpdata_batch *b, int64_t *cycles_out, int32_t nseg);
+
+/* Mass of grid i (as mpdata_mass); synchronises the stream. */
+int mpdata_batch_mass(mpdata_batch *b, int32_t i, double *out);
+
+int mpdata_batch_sync(mpdata_batch *b);
+void mpdata_batch_destroy(mpdata_batch *b);                 /* NULL-safe */
+const char *mpdata_batch_last_error(const mpdata_batch *b); /* NULL: last create */
 
 /* Version of this ABI (MPDATA_ABI_VERSION). */
 int mpdata_abi_version(void);

@@ -24,6 +24,7 @@ MPDATA_FP64 = 0
 MPDATA_FP32 = 1
 MPDATA_BC_PERIODIC = 0
 MPDATA_BC_OPEN = 1
+MPDATA_FLAG_NO_GRAPH = 1
 
 ERRORS = {MPDATA_EINVAL: "EINVAL", MPDATA_ENOMEM: "ENOMEM", MPDATA_EDEVICE: "EDEVICE",
           MPDATA_ENOTSUP: "ENOTSUP", MPDATA_ENONFINITE: "ENONFINITE"}
@@ -32,7 +33,14 @@ ERRORS = {MPDATA_EINVAL: "EINVAL", MPDATA_ENOMEM: "ENOMEM", MPDATA_EDEVICE: "EDE
 class mpdata_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("bc", ctypes.c_int32), ("iord", ctypes.c_int32),
-                ("nonos", ctypes.c_int32), ("tile", ctypes.c_int32), ("eps", ctypes.c_double)]
+                ("nonos", ctypes.c_int32), ("tile", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("eps", ctypes.c_double)]
+
+
+class mpdata_plan(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("nwg", ctypes.c_int32), ("nseg", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seg", ctypes.POINTER(ctypes.c_int32)),
+                ("wg_begin", ctypes.POINTER(ctypes.c_int32))]
 
 
 class MpdataError(RuntimeError):
@@ -62,6 +70,28 @@ _SIGNATURES = {
     "mpdata_steps_done": ([ctypes.c_void_p], ctypes.c_int64),
     "mpdata_destroy": ([ctypes.c_void_p], None),
     "mpdata_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
+    "mpdata_occupancy": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+                         ctypes.c_int),
+    "mpdata_batch_workspace_bytes": ([ctypes.c_int32, ctypes.POINTER(mpdata_params),
+                                      ctypes.c_int32, ctypes.c_int32], ctypes.c_size_t),
+    "mpdata_batch_default_plan_size": ([ctypes.c_int32, ctypes.POINTER(mpdata_params),
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "mpdata_batch_create": ([ctypes.c_int32, ctypes.POINTER(mpdata_params),
+                             ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                             ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                             ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_size_t,
+                             ctypes.c_void_p, ctypes.POINTER(mpdata_plan),
+                             ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "mpdata_batch_step": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int),
+    "mpdata_batch_profile_step": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.c_int32], ctypes.c_int),
+    "mpdata_batch_mass": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+                          ctypes.c_int),
+    "mpdata_batch_sync": ([ctypes.c_void_p], ctypes.c_int),
+    "mpdata_batch_destroy": ([ctypes.c_void_p], None),
+    "mpdata_batch_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
 }
 
 
@@ -93,9 +123,10 @@ def hip_runtimes_mapped():
     return sorted(paths)
 
 
-def check(code: int, ctx=None):
+def check(code: int, ctx=None, batch=False):
     if code != MPDATA_OK:
-        msg = load().mpdata_last_error(ctx).decode(errors="replace")
+        fn = load().mpdata_batch_last_error if batch else load().mpdata_last_error
+        msg = fn(ctx).decode(errors="replace")
         raise MpdataError(code, msg)
 
 
@@ -159,3 +190,83 @@ def mpdata_destroy(ctx):
 
 def mpdata_last_error(ctx=None) -> str:
     return load().mpdata_last_error(ctx).decode(errors="replace")
+
+
+def mpdata_occupancy(dtype: int, tile: int, bc: int, nonos: int):
+    per, cus = ctypes.c_int32(), ctypes.c_int32()
+    check(load().mpdata_occupancy(dtype, tile, bc, nonos, ctypes.byref(per), ctypes.byref(cus)))
+    return per.value, cus.value
+
+
+# ------------------------------------------------------------------ batches
+
+def _params_array(params):
+    arr = (mpdata_params * len(params))(*params)
+    return arr
+
+
+def mpdata_batch_workspace_bytes(params, max_segments: int = 0, max_wg: int = 0) -> int:
+    arr = _params_array(params)
+    return int(load().mpdata_batch_workspace_bytes(len(params), arr, max_segments, max_wg))
+
+
+def mpdata_batch_default_plan_size(params, tile: int = 0):
+    arr = _params_array(params)
+    nseg, nwg = ctypes.c_int32(), ctypes.c_int32()
+    check(load().mpdata_batch_default_plan_size(len(params), arr, tile, ctypes.byref(nseg),
+                                                ctypes.byref(nwg)))
+    return nseg.value, nwg.value
+
+
+def make_plan(tile: int, seg, wg_begin):
+    """mpdata_plan over host int32 arrays (seg: nseg x 5, wg_begin: nwg + 1);
+    returns (plan, keepalive)."""
+    import numpy as np
+    seg = np.ascontiguousarray(seg, dtype=np.int32).reshape(-1, 5)
+    wg_begin = np.ascontiguousarray(wg_begin, dtype=np.int32)
+    plan = mpdata_plan(tile, len(wg_begin) - 1, len(seg), 0,
+                       seg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                       wg_begin.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return plan, (seg, wg_begin)
+
+
+def mpdata_batch_create(params, psi, u1, u2, u3, h, workspace, ws_bytes, stream, plan=None):
+    n = len(params)
+    arr = _params_array(params)
+    vp = lambda xs: (ctypes.c_void_p * n)(*xs)
+    out = ctypes.c_void_p()
+    code = load().mpdata_batch_create(n, arr, vp(psi), vp(u1), vp(u2), vp(u3), vp(h), workspace,
+                                      ws_bytes, stream, ctypes.byref(plan) if plan else None,
+                                      ctypes.byref(out))
+    check(code, None, batch=True)
+    return out.value
+
+
+def mpdata_batch_step(b, nsteps: int):
+    check(load().mpdata_batch_step(b, nsteps), b, batch=True)
+
+
+def mpdata_batch_profile_step(b, nseg: int):
+    import numpy as np
+    out = np.zeros(nseg, dtype=np.int64)
+    check(load().mpdata_batch_profile_step(b, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                           nseg), b, batch=True)
+    return out
+
+
+def mpdata_batch_mass(b, i: int) -> float:
+    out = ctypes.c_double()
+    check(load().mpdata_batch_mass(b, i, ctypes.byref(out)), b, batch=True)
+    return out.value
+
+
+def mpdata_batch_sync(b):
+    check(load().mpdata_batch_sync(b), b, batch=True)
+
+
+def mpdata_batch_destroy(b):
+    load().mpdata_batch_destroy(b)
+
+
+def mpdata_batch_last_error(b=None) -> str:
+    return load().mpdata_batch_last_error(b).decode(errors="replace")

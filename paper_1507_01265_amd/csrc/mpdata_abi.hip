@@ -1,8 +1,11 @@
 // mpdata_abi.hip -- host side of the libmpdata C ABI (include/mpdata.h).
 //
-// Validation, workspace layout, the time loop (ping-pong between the
-// caller's psi and the workspace copy) and the mass reduction.  No device
-// memory is allocated here: the caller provides every buffer.
+// Validation, workspace layout, launch plans (which workgroup of the
+// persistent step kernel runs which (grid, tile, z-range) segment), the
+// time loop (ping-pong between the caller's psi and a workspace copy, runs
+// of steps replayed from a hipGraph), batches of grids and the mass
+// reduction.  No device memory is allocated here: the caller provides every
+// buffer, including the workspace that holds the plan.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -10,7 +13,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "../../include/mpdata.h"
 #include "mpdata_kernels.h"
@@ -19,14 +24,12 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMassParts = 1024;  // blocks of the mass reduction (fixed: deterministic)
+constexpr int kGraphSteps = 8;    // steps per replayed graph (even: psi ends where it began)
+constexpr int kXcds = 8;          // XCDs of an MI355X; workgroup w runs on XCD w % 8
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 thread_local char g_create_err[256];
-
-struct Layout {
-    size_t psi2, partials, result, flags, total;
-};
 
 size_t cells_of(const mpdata_params *p)
 {
@@ -35,27 +38,17 @@ size_t cells_of(const mpdata_params *p)
 
 size_t word_of(const mpdata_params *p) { return p->dtype == MPDATA_FP32 ? 4 : 8; }
 
-Layout layout_of(const mpdata_params *p)
+const mpd::TileShape &shape_of(int tile)
 {
-    Layout l;
-    size_t off = 0;
-    l.psi2 = off;
-    off += align_up(cells_of(p) * word_of(p));
-    l.partials = off;
-    off += align_up((size_t)kMassParts * 2 * sizeof(double));
-    l.result = off;
-    off += align_up(2 * sizeof(double));
-    l.flags = off;
-    off += align_up(4 * sizeof(unsigned int));
-    l.total = off;
-    return l;
+    int count = 0;
+    return mpd::tile_shapes(&count)[tile - 1];
 }
 
 // Default launch shape per precision: the largest region whose register
 // footprint fits the workgroup without spilling.
-int default_tile(const mpdata_params *p) { return p->dtype == MPDATA_FP32 ? 2 : 4; }
+int default_tile(int dtype) { return dtype == MPDATA_FP32 ? 5 : 4; }
 
-int planes_per_chunk(const mpdata_params *p) { return p->nz; }
+int tile_of(const mpdata_params *p) { return p->tile ? p->tile : default_tile(p->dtype); }
 
 const char *check_params(const mpdata_params *p)
 {
@@ -72,6 +65,8 @@ const char *check_params(const mpdata_params *p)
     if (p->nonos != 0 && p->nonos != 1) return "nonos must be 0 or 1";
     if (p->nonos && p->iord != 2) return "nonos needs iord 2";
     if (!(p->eps > 0.0) || !isfinite(p->eps)) return "eps must be finite and > 0";
+    if (p->flags & ~MPDATA_FLAG_NO_GRAPH) return "unknown flag bits";
+    if (p->reserved != 0) return "reserved must be 0";
     int count = 0;
     mpd::tile_shapes(&count);
     if (p->tile < 0 || p->tile > count) return "tile id out of range";
@@ -80,23 +75,177 @@ const char *check_params(const mpdata_params *p)
 
 bool misaligned(const void *ptr) { return ((uintptr_t)ptr & 15u) != 0; }
 
+// ----------------------------------------------------------------- plans
+
+int tiles_x(const mpdata_params &p, int tile) { return (p.nx + shape_of(tile).rx - 5) / (shape_of(tile).rx - 4); }
+int tiles_y(const mpdata_params &p, int tile) { return (p.ny + shape_of(tile).ry - 5) / (shape_of(tile).ry - 4); }
+
+// Default plan: the work of all grids, counted in (tile, plane) units and
+// listed tile by tile (grid, then tile row, then tile), is cut into nwg
+// contiguous, equal shares.  Consecutive shares go to workgroups of the same
+// XCD (workgroup w runs on XCD w % 8), so neighbouring tiles -- which re-read
+// each other's halo -- share an L2.
+void default_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
+                  std::vector<mpd::Segment> &segs, std::vector<int> &wg_begin)
+{
+    struct Tile {
+        int grid, tx, ty, nz;
+    };
+    std::vector<Tile> tiles;
+    long long work = 0;
+    for (int g = 0; g < (int)grids.size(); ++g) {
+        const int ntx = tiles_x(grids[g], tile), nty = tiles_y(grids[g], tile);
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx) {
+                tiles.push_back({g, tx, ty, grids[g].nz});
+                work += grids[g].nz;
+            }
+    }
+    // logical share l covers work units [l*work/nwg, (l+1)*work/nwg)
+    std::vector<std::vector<mpd::Segment>> share(nwg);
+    size_t ti = 0;
+    long long tile_start = 0;  // work offset of tiles[ti]
+    for (int l = 0; l < nwg; ++l) {
+        const long long a = work * l / nwg, b = work * (l + 1) / nwg;
+        long long pos = a;
+        while (pos < b && ti < tiles.size()) {
+            const Tile &t = tiles[ti];
+            const long long t_end = tile_start + t.nz;
+            const long long e = std::min(b, t_end);
+            mpd::Segment s{};
+            s.grid = t.grid;
+            s.tx = t.tx;
+            s.ty = t.ty;
+            s.z0 = (int)(pos - tile_start);
+            s.z1 = (int)(e - tile_start);
+            share[l].push_back(s);
+            pos = e;
+            if (e == t_end) {
+                tile_start = t_end;
+                ++ti;
+            }
+        }
+    }
+    const int per_xcd = nwg % kXcds == 0 ? nwg / kXcds : 0;
+    segs.clear();
+    wg_begin.assign(nwg + 1, 0);
+    for (int w = 0; w < nwg; ++w) {
+        const int l = per_xcd ? (w % kXcds) * per_xcd + w / kXcds : w;
+        wg_begin[w] = (int)segs.size();
+        segs.insert(segs.end(), share[l].begin(), share[l].end());
+    }
+    wg_begin[nwg] = (int)segs.size();
+}
+
+// A plan must cover every output tile of every grid over all its planes
+// exactly once.
+const char *check_plan(const std::vector<mpdata_params> &grids, int tile,
+                       const std::vector<mpd::Segment> &segs, const std::vector<int> &wg_begin)
+{
+    const int nwg = (int)wg_begin.size() - 1;
+    if (nwg < 1 || wg_begin[0] != 0 || wg_begin[nwg] != (int)segs.size()) return "bad wg_begin";
+    for (int w = 0; w < nwg; ++w)
+        if (wg_begin[w + 1] < wg_begin[w]) return "wg_begin must be non-decreasing";
+    std::vector<size_t> base(grids.size() + 1, 0);
+    for (size_t g = 0; g < grids.size(); ++g)
+        base[g + 1] = base[g] + (size_t)tiles_x(grids[g], tile) * tiles_y(grids[g], tile) * grids[g].nz;
+    std::vector<unsigned char> seen(base.back(), 0);
+    for (const mpd::Segment &s : segs) {
+        if (s.grid < 0 || s.grid >= (int)grids.size()) return "segment grid out of range";
+        const mpdata_params &p = grids[s.grid];
+        const int ntx = tiles_x(p, tile), nty = tiles_y(p, tile);
+        if (s.tx < 0 || s.tx >= ntx || s.ty < 0 || s.ty >= nty) return "segment tile out of range";
+        if (s.z0 < 0 || s.z1 > p.nz || s.z0 >= s.z1) return "segment z-range out of range";
+        for (int z = s.z0; z < s.z1; ++z) {
+            unsigned char &c = seen[base[s.grid] + ((size_t)s.ty * ntx + s.tx) * p.nz + z];
+            if (c) return "a (tile, plane) is covered twice";
+            c = 1;
+        }
+    }
+    for (unsigned char c : seen)
+        if (!c) return "a (tile, plane) is not covered";
+    return nullptr;
+}
+
+struct Layout {
+    size_t psi2, grids, segs, wg, ticks, partials, result, flags, total;
+};
+
+Layout layout_for(const std::vector<mpdata_params> &grids, int max_segs, int max_wg)
+{
+    Layout l;
+    size_t off = 0;
+    l.psi2 = off;
+    for (const mpdata_params &p : grids) off += align_up(cells_of(&p) * word_of(&p));
+    l.grids = off;
+    off += align_up(grids.size() * sizeof(mpd::GridDesc<double>));
+    l.segs = off;
+    off += align_up((size_t)max_segs * sizeof(mpd::Segment));
+    l.wg = off;
+    off += align_up(((size_t)max_wg + 1) * sizeof(int));
+    l.ticks = off;
+    off += align_up((size_t)max_segs * sizeof(long long));
+    l.partials = off;
+    off += align_up((size_t)kMassParts * 2 * sizeof(double));
+    l.result = off;
+    off += align_up(2 * sizeof(double));
+    l.flags = off;
+    off += align_up(4 * sizeof(unsigned int));
+    l.total = off;
+    return l;
+}
+
+int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return cus;
+}
+
+int wg_per_cu(int dtype, int tile, bool open, bool nonos)
+{
+    const void *k = dtype == MPDATA_FP32 ? mpd::step_kernel_ptr<float>(tile, open, nonos)
+                                         : mpd::step_kernel_ptr<double>(tile, open, nonos);
+    int per = 0;
+    const mpd::TileShape &s = shape_of(tile);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, s.rx * s.ry, 0) != hipSuccess)
+        return 0;
+    return per;
+}
+
+// Largest plan of the default kind: one segment per tile and per workgroup
+// boundary.
+void default_plan_bounds(const std::vector<mpdata_params> &grids, int tile, int nwg, int *nseg)
+{
+    long long n = 0;
+    for (const mpdata_params &p : grids) n += (long long)tiles_x(p, tile) * tiles_y(p, tile);
+    *nseg = (int)(n + nwg);
+}
+
 }  // namespace
 
-struct mpdata_ctx {
-    mpdata_params p;
-    void *psi;
-    const void *u1, *u2, *u3, *h;
+// ================================================================== engine
+// What one launch of the persistent kernel needs, shared by contexts and
+// batches.
+
+struct Engine {
+    int dtype, tile, nwg, nseg, ngrids, iord;
+    bool open, nonos, use_graph;
+    double eps;
+    hipStream_t stream;
     char *ws;
     Layout lay;
-    hipStream_t stream;
-    int tile;
-    int64_t steps;
+    std::vector<mpdata_params> params;
+    std::vector<mpd::GridDesc<double>> grids;  // host copy (float grids reinterpret the pointers)
+    hipGraphExec_t graph = nullptr;            // kGraphSteps steps
+    hipGraph_t graph_def = nullptr;
     char err[256];
 };
 
-static int fail(mpdata_ctx *c, int code, const char *fmt, ...)
+static int fail_to(char *dst, int code, const char *fmt, ...)
 {
-    char *dst = c ? c->err : g_create_err;
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(dst, 256, fmt, ap);
@@ -104,36 +253,272 @@ static int fail(mpdata_ctx *c, int code, const char *fmt, ...)
     return code;
 }
 
-static int hip_fail(mpdata_ctx *c, hipError_t e, const char *what)
+static hipError_t launch_one(Engine &e, int flip, long long *ticks)
 {
-    return fail(c, MPDATA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    if (e.iord == 1) {
+        const mpd::GridDesc<double> &g = e.grids[0];
+        if (e.dtype == MPDATA_FP32) {
+            mpd::DonorArgs<float> a{(const float *)g.psi[flip], (float *)g.psi[1 - flip],
+                                    (const float *)g.u1, (const float *)g.u2, (const float *)g.u3,
+                                    (const float *)g.h, g.nx, g.ny, g.nz};
+            return mpd::launch_donor<float>(a, e.open, e.stream);
+        }
+        mpd::DonorArgs<double> a{g.psi[flip], g.psi[1 - flip], g.u1, g.u2, g.u3, g.h,
+                                 g.nx, g.ny, g.nz};
+        return mpd::launch_donor<double>(a, e.open, e.stream);
+    }
+    const mpd::Segment *segs = (const mpd::Segment *)(e.ws + e.lay.segs);
+    const int *wg = (const int *)(e.ws + e.lay.wg);
+    if (e.dtype == MPDATA_FP32)
+        return mpd::launch_persistent<float>((const mpd::GridDesc<float> *)(e.ws + e.lay.grids),
+                                             segs, wg, e.nwg, e.tile, e.open, e.nonos, flip,
+                                             e.eps, ticks, e.stream);
+    return mpd::launch_persistent<double>((const mpd::GridDesc<double> *)(e.ws + e.lay.grids),
+                                          segs, wg, e.nwg, e.tile, e.open, e.nonos, flip, e.eps,
+                                          ticks, e.stream);
 }
 
-template <typename T> static hipError_t run_steps(mpdata_ctx *c, int32_t nsteps)
+// Graph of kGraphSteps step launches (each reading what the previous wrote).
+static hipError_t build_graph(Engine &e)
 {
-    const mpdata_params &p = c->p;
-    T *bufs[2] = {(T *)c->psi, (T *)(c->ws + c->lay.psi2)};
-    mpd::StepArgs<T> a;
-    a.u1 = (const T *)c->u1;
-    a.u2 = (const T *)c->u2;
-    a.u3 = (const T *)c->u3;
-    a.h = (const T *)c->h;
-    a.nx = p.nx;
-    a.ny = p.ny;
-    a.nz = p.nz;
-    a.zlen = planes_per_chunk(&p);
-    a.eps = p.eps;
-    for (int32_t s = 0; s < nsteps; ++s) {
-        a.psi_in = bufs[s & 1];
-        a.psi_out = bufs[(s + 1) & 1];
-        hipError_t e = mpd::launch_step<T>(a, c->tile, p.iord, p.bc == MPDATA_BC_OPEN,
-                                           p.nonos != 0, c->stream);
-        if (e != hipSuccess) return e;
+    hipError_t r = hipGraphCreate(&e.graph_def, 0);
+    if (r != hipSuccess) return r;
+    hipGraphNode_t prev = nullptr;
+    const mpd::TileShape &sh = shape_of(e.tile);
+    const void *gridp = e.ws + e.lay.grids;
+    const void *segp = e.ws + e.lay.segs;
+    const void *wgp = e.ws + e.lay.wg;
+    long long *no_ticks = nullptr;
+    int flips[kGraphSteps];
+    for (int s = 0; s < kGraphSteps; ++s) {
+        flips[s] = s & 1;
+        void *args[] = {(void *)&gridp, (void *)&segp, (void *)&wgp, (void *)&flips[s],
+                        (void *)&e.eps, (void *)&no_ticks};
+        hipKernelNodeParams kp{};
+        kp.func = (void *)(e.dtype == MPDATA_FP32 ? mpd::step_kernel_ptr<float>(e.tile, e.open, e.nonos)
+                                                  : mpd::step_kernel_ptr<double>(e.tile, e.open, e.nonos));
+        kp.gridDim = dim3(e.nwg);
+        kp.blockDim = dim3(sh.rx * sh.ry);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        r = hipGraphAddKernelNode(&node, e.graph_def, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (r != hipSuccess) return r;
+        prev = node;
     }
-    if (nsteps & 1)
-        return hipMemcpyAsync(bufs[0], bufs[1], cells_of(&p) * sizeof(T), hipMemcpyDeviceToDevice,
-                              c->stream);
-    return hipSuccess;
+    return hipGraphInstantiate(&e.graph, e.graph_def, nullptr, nullptr, 0);
+}
+
+static int engine_step(Engine &e, int32_t nsteps)
+{
+    if (nsteps < 0) return fail_to(e.err, MPDATA_EINVAL, "nsteps must be >= 0");
+    hipError_t r = hipSuccess;
+    int32_t done = 0;
+    if (e.use_graph && e.iord == 2 && nsteps >= kGraphSteps) {
+        if (!e.graph) {
+            r = build_graph(e);
+            if (r != hipSuccess) {
+                e.use_graph = false;  // fall back to plain launches of the same kernel
+                if (e.graph) hipGraphExecDestroy(e.graph);
+                if (e.graph_def) hipGraphDestroy(e.graph_def);
+                e.graph = nullptr;
+                e.graph_def = nullptr;
+                (void)hipGetLastError();
+            }
+        }
+        while (e.graph && nsteps - done >= kGraphSteps) {
+            r = hipGraphLaunch(e.graph, e.stream);
+            if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(r));
+            done += kGraphSteps;
+        }
+    }
+    for (int32_t s = done; s < nsteps; ++s) {
+        r = launch_one(e, (s - done) & 1, nullptr);
+        if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "step launch: %s", hipGetErrorString(r));
+    }
+    if ((nsteps - done) & 1) {
+        r = e.dtype == MPDATA_FP32
+                ? mpd::launch_copy_back<float>((const mpd::GridDesc<float> *)(e.ws + e.lay.grids), e.ngrids, e.stream)
+                : mpd::launch_copy_back<double>((const mpd::GridDesc<double> *)(e.ws + e.lay.grids), e.ngrids, e.stream);
+        if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "copy back: %s", hipGetErrorString(r));
+    }
+    return MPDATA_OK;
+}
+
+static int engine_mass(Engine &e, int i, double *out)
+{
+    double *parts = (double *)(e.ws + e.lay.partials);
+    double *res = (double *)(e.ws + e.lay.result);
+    const mpd::GridDesc<double> &g = e.grids[i];
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    hipError_t r = e.dtype == MPDATA_FP64
+                       ? mpd::launch_mass<double>(g.psi[0], g.h, n, parts, kMassParts, res, e.stream)
+                       : mpd::launch_mass<float>((const float *)g.psi[0], (const float *)g.h, n,
+                                                 parts, kMassParts, res, e.stream);
+    if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "mass launch: %s", hipGetErrorString(r));
+    double h2[2];
+    r = hipMemcpyAsync(h2, res, sizeof(h2), hipMemcpyDeviceToHost, e.stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(e.stream);
+    if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "mass readback: %s", hipGetErrorString(r));
+    *out = h2[0];
+    if (!isfinite(h2[0])) return fail_to(e.err, MPDATA_ENONFINITE, "psi holds NaN or Inf");
+    return MPDATA_OK;
+}
+
+// Validates every grid's arrays on the device (h > 0 and finite; periodic
+// faces n == 0), lays out the workspace, uploads descriptors and the plan.
+static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *params,
+                       void *const *psi, const void *const *u1, const void *const *u2,
+                       const void *const *u3, const void *const *h, void *workspace,
+                       size_t ws_bytes, void *stream, const mpdata_plan *plan, bool batch)
+{
+    if (n < 1) return fail_to(errbuf, MPDATA_EINVAL, "need at least one grid");
+    if (!params) return fail_to(errbuf, MPDATA_EINVAL, "params is NULL");
+    if (!psi || !u1 || !u2 || !u3 || !h) return fail_to(errbuf, MPDATA_EINVAL, "NULL array list");
+    for (int i = 0; i < n; ++i) {
+        if (const char *m = check_params(&params[i]))
+            return fail_to(errbuf, MPDATA_EINVAL, "grid %d: %s", i, m);
+        if (!psi[i] || !u1[i] || !u2[i] || !u3[i] || !h[i])
+            return fail_to(errbuf, MPDATA_EINVAL, "grid %d: NULL array or workspace pointer", i);
+        if (misaligned(psi[i]) || misaligned(u1[i]) || misaligned(u2[i]) || misaligned(u3[i]) ||
+            misaligned(h[i]))
+            return fail_to(errbuf, MPDATA_EINVAL, "grid %d: arrays must be 16-byte aligned", i);
+        const mpdata_params &a = params[0], &b = params[i];
+        if (a.dtype != b.dtype || a.bc != b.bc || a.iord != b.iord || a.nonos != b.nonos ||
+            a.eps != b.eps || a.tile != b.tile)
+            return fail_to(errbuf, MPDATA_ENOTSUP,
+                           "grid %d: a batch shares dtype, bc, iord, nonos, eps and tile", i);
+    }
+    if (batch && params[0].iord != 2)
+        return fail_to(errbuf, MPDATA_ENOTSUP, "batches run the full step (iord 2)");
+    if (!workspace) return fail_to(errbuf, MPDATA_EINVAL, "NULL array or workspace pointer");
+    if (((uintptr_t)workspace & (kAlign - 1)) != 0)
+        return fail_to(errbuf, MPDATA_EINVAL, "workspace must be 256-byte aligned");
+
+    e.params.assign(params, params + n);
+    e.dtype = params[0].dtype;
+    e.iord = params[0].iord;
+    e.open = params[0].bc == MPDATA_BC_OPEN;
+    e.nonos = params[0].nonos != 0;
+    e.eps = params[0].eps;
+    e.use_graph = !(params[0].flags & MPDATA_FLAG_NO_GRAPH);
+    e.stream = (hipStream_t)stream;
+    e.ngrids = n;
+    e.ws = (char *)workspace;
+    e.err[0] = 0;
+
+    std::vector<mpd::Segment> segs;
+    std::vector<int> wg;
+    if (plan) {
+        if (plan->tile < 1 || plan->tile > mpdata_tile_count() || plan->nwg < 1 || plan->nseg < 1 ||
+            !plan->seg || !plan->wg_begin || plan->reserved != 0)
+            return fail_to(errbuf, MPDATA_EINVAL, "invalid plan header");
+        e.tile = plan->tile;
+        segs.resize(plan->nseg);
+        for (int s = 0; s < plan->nseg; ++s) {
+            const int32_t *v = plan->seg + 5 * (size_t)s;
+            segs[s] = mpd::Segment{v[0], v[1], v[2], v[3], v[4], 0, 0, 0};
+        }
+        wg.assign(plan->wg_begin, plan->wg_begin + plan->nwg + 1);
+    } else {
+        e.tile = tile_of(&params[0]);
+        const int per = wg_per_cu(e.dtype, e.tile, e.open, e.nonos);
+        const int cus = device_cus();
+        if (per < 1 || cus < 1) return fail_to(errbuf, MPDATA_EDEVICE, "occupancy query failed");
+        default_plan(e.params, e.tile, per * cus, segs, wg);
+    }
+    if (const char *m = check_plan(e.params, e.tile, segs, wg))
+        return fail_to(errbuf, MPDATA_EINVAL, "plan: %s", m);
+    e.nwg = (int)wg.size() - 1;
+    e.nseg = (int)segs.size();
+    e.lay = layout_for(e.params, e.nseg, e.nwg);
+    if (ws_bytes < e.lay.total)
+        return fail_to(errbuf, MPDATA_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes,
+                       e.lay.total);
+
+    hipError_t r;
+    unsigned int *flags = (unsigned int *)(e.ws + e.lay.flags);
+    size_t off2 = e.lay.psi2;
+    e.grids.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const mpdata_params &p = params[i];
+        mpd::GridDesc<double> &g = e.grids[i];
+        g.u1 = (const double *)u1[i];
+        g.u2 = (const double *)u2[i];
+        g.u3 = (const double *)u3[i];
+        g.h = (const double *)h[i];
+        g.psi[0] = (double *)psi[i];
+        g.psi[1] = (double *)(e.ws + off2);
+        g.nx = p.nx;
+        g.ny = p.ny;
+        g.nz = p.nz;
+        g.pad = 0;
+        off2 += align_up(cells_of(&p) * word_of(&p));
+
+        r = hipMemsetAsync(flags, 0, 4 * sizeof(unsigned int), e.stream);
+        if (r != hipSuccess) return fail_to(errbuf, MPDATA_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(r));
+        const int periodic = p.bc == MPDATA_BC_PERIODIC;
+        r = e.dtype == MPDATA_FP64
+                ? mpd::launch_validate<double>(g.h, g.u1, g.u2, g.u3, p.nx, p.ny, p.nz, periodic, flags, e.stream)
+                : mpd::launch_validate<float>((const float *)g.h, (const float *)g.u1,
+                                              (const float *)g.u2, (const float *)g.u3, p.nx, p.ny,
+                                              p.nz, periodic, flags, e.stream);
+        if (r != hipSuccess) return fail_to(errbuf, MPDATA_EDEVICE, "validate launch: %s", hipGetErrorString(r));
+        unsigned int hf[2] = {0, 0};
+        r = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, e.stream);
+        if (r == hipSuccess) r = hipStreamSynchronize(e.stream);
+        if (r != hipSuccess) return fail_to(errbuf, MPDATA_EDEVICE, "validate readback: %s", hipGetErrorString(r));
+        if (hf[0]) return fail_to(errbuf, MPDATA_EINVAL, "grid %d: h must be finite and > 0 (%u bad cells)", i, hf[0]);
+        if (hf[1])
+            return fail_to(errbuf, MPDATA_EINVAL,
+                           "grid %d: periodic boundaries need face n == face 0 on every axis (%u differ)",
+                           i, hf[1]);
+    }
+    // descriptors and plan into the workspace (GridDesc<float> has the same layout)
+    r = hipMemcpyAsync(e.ws + e.lay.grids, e.grids.data(), n * sizeof(mpd::GridDesc<double>),
+                       hipMemcpyHostToDevice, e.stream);
+    if (r == hipSuccess)
+        r = hipMemcpyAsync(e.ws + e.lay.segs, segs.data(), segs.size() * sizeof(mpd::Segment),
+                           hipMemcpyHostToDevice, e.stream);
+    if (r == hipSuccess)
+        r = hipMemcpyAsync(e.ws + e.lay.wg, wg.data(), wg.size() * sizeof(int),
+                           hipMemcpyHostToDevice, e.stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(e.stream);
+    if (r != hipSuccess) return fail_to(errbuf, MPDATA_EDEVICE, "plan upload: %s", hipGetErrorString(r));
+    return MPDATA_OK;
+}
+
+static void engine_release(Engine &e)
+{
+    if (e.graph) hipGraphExecDestroy(e.graph);
+    if (e.graph_def) hipGraphDestroy(e.graph_def);
+    e.graph = nullptr;
+    e.graph_def = nullptr;
+}
+
+struct mpdata_ctx {
+    Engine e;
+    int64_t steps;
+};
+
+struct mpdata_batch {
+    Engine e;
+};
+
+static size_t workspace_for(int n, const mpdata_params *params, int max_segs, int max_wg)
+{
+    std::vector<mpdata_params> v(params, params + n);
+    return layout_for(v, max_segs, max_wg).total;
+}
+
+// Upper bound of the default plan's size without touching the device: at
+// most 8 resident workgroups of the largest shape per CU on 256 CUs.
+static void default_bounds(int n, const mpdata_params *params, int tile, int *nseg, int *nwg)
+{
+    std::vector<mpdata_params> v(params, params + n);
+    *nwg = 256 * 8;
+    default_plan_bounds(v, tile, *nwg, nseg);
 }
 
 extern "C" {
@@ -158,10 +543,26 @@ int mpdata_tile_info(int32_t id, int32_t *tx, int32_t *ty, int32_t *threads)
     return MPDATA_OK;
 }
 
+int mpdata_occupancy(int32_t dtype, int32_t tile, int32_t bc, int32_t nonos, int32_t *per_cu,
+                     int32_t *cus)
+{
+    if (dtype != MPDATA_FP64 && dtype != MPDATA_FP32) return MPDATA_EINVAL;
+    if (tile == 0) tile = default_tile(dtype);
+    if (tile < 1 || tile > mpdata_tile_count()) return MPDATA_EINVAL;
+    const int per = wg_per_cu(dtype, tile, bc == MPDATA_BC_OPEN, nonos != 0);
+    const int c = device_cus();
+    if (per < 1 || c < 1) return MPDATA_EDEVICE;
+    if (per_cu) *per_cu = per;
+    if (cus) *cus = c;
+    return MPDATA_OK;
+}
+
 size_t mpdata_workspace_bytes(const mpdata_params *p)
 {
     if (check_params(p)) return 0;
-    return layout_of(p).total;
+    int nseg = 0, nwg = 0;
+    default_bounds(1, p, tile_of(p), &nseg, &nwg);
+    return workspace_for(1, p, nseg, nwg);
 }
 
 int mpdata_create(const mpdata_params *p, void *psi, const void *u1, const void *u2,
@@ -169,57 +570,27 @@ int mpdata_create(const mpdata_params *p, void *psi, const void *u1, const void 
                   mpdata_ctx **out)
 {
     g_create_err[0] = 0;
-    if (!out) return fail(nullptr, MPDATA_EINVAL, "out is NULL");
+    if (!out) return fail_to(g_create_err, MPDATA_EINVAL, "out is NULL");
     *out = nullptr;
-    if (const char *m = check_params(p)) return fail(nullptr, MPDATA_EINVAL, "%s", m);
+    if (const char *m = check_params(p)) return fail_to(g_create_err, MPDATA_EINVAL, "%s", m);
     if (!psi || !u1 || !u2 || !u3 || !h || !workspace)
-        return fail(nullptr, MPDATA_EINVAL, "NULL array or workspace pointer");
+        return fail_to(g_create_err, MPDATA_EINVAL, "NULL array or workspace pointer");
     if (misaligned(psi) || misaligned(u1) || misaligned(u2) || misaligned(u3) || misaligned(h))
-        return fail(nullptr, MPDATA_EINVAL, "arrays must be 16-byte aligned");
-    if (((uintptr_t)workspace & (kAlign - 1)) != 0)
-        return fail(nullptr, MPDATA_EINVAL, "workspace must be 256-byte aligned");
-    const Layout lay = layout_of(p);
-    if (ws_bytes < lay.total)
-        return fail(nullptr, MPDATA_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes,
-                    lay.total);
-
-    hipStream_t s = (hipStream_t)stream;
-    char *ws = (char *)workspace;
-    unsigned int *flags = (unsigned int *)(ws + lay.flags);
-    hipError_t e = hipMemsetAsync(flags, 0, 4 * sizeof(unsigned int), s);
-    if (e != hipSuccess) return hip_fail(nullptr, e, "hipMemsetAsync");
-    const int periodic = p->bc == MPDATA_BC_PERIODIC;
-    if (p->dtype == MPDATA_FP64)
-        e = mpd::launch_validate<double>((const double *)h, (const double *)u1,
-                                         (const double *)u2, (const double *)u3, p->nx, p->ny,
-                                         p->nz, periodic, flags, s);
-    else
-        e = mpd::launch_validate<float>((const float *)h, (const float *)u1, (const float *)u2,
-                                        (const float *)u3, p->nx, p->ny, p->nz, periodic, flags, s);
-    if (e != hipSuccess) return hip_fail(nullptr, e, "validate launch");
-    unsigned int hflags[2] = {0, 0};
-    e = hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(nullptr, e, "validate readback");
-    if (hflags[0]) return fail(nullptr, MPDATA_EINVAL, "h must be finite and > 0 (%u bad cells)", hflags[0]);
-    if (hflags[1])
-        return fail(nullptr, MPDATA_EINVAL,
-                    "periodic boundaries need face n == face 0 on every axis (%u differ)", hflags[1]);
-
+        return fail_to(g_create_err, MPDATA_EINVAL, "arrays must be 16-byte aligned");
+    if (ws_bytes < mpdata_workspace_bytes(p))
+        return fail_to(g_create_err, MPDATA_ENOMEM, "workspace too small: %zu < %zu bytes",
+                       ws_bytes, mpdata_workspace_bytes(p));
     mpdata_ctx *c = new (std::nothrow) mpdata_ctx;
-    if (!c) return fail(nullptr, MPDATA_ENOMEM, "host allocation failed");
-    c->p = *p;
-    c->psi = psi;
-    c->u1 = u1;
-    c->u2 = u2;
-    c->u3 = u3;
-    c->h = h;
-    c->ws = ws;
-    c->lay = lay;
-    c->stream = s;
-    c->tile = p->tile ? p->tile : default_tile(p);
+    if (!c) return fail_to(g_create_err, MPDATA_ENOMEM, "host allocation failed");
+    void *psis[1] = {psi};
+    const void *a1[1] = {u1}, *a2[1] = {u2}, *a3[1] = {u3}, *ah[1] = {h};
+    const int rc = engine_init(c->e, g_create_err, 1, p, psis, a1, a2, a3, ah, workspace, ws_bytes,
+                               stream, nullptr, false);
+    if (rc != MPDATA_OK) {
+        delete c;
+        return rc;
+    }
     c->steps = 0;
-    c->err[0] = 0;
     *out = c;
     return MPDATA_OK;
 }
@@ -227,54 +598,35 @@ int mpdata_create(const mpdata_params *p, void *psi, const void *u1, const void 
 int mpdata_step(mpdata_ctx *c, int32_t nsteps)
 {
     if (!c) return MPDATA_EINVAL;
-    if (nsteps < 0) return fail(c, MPDATA_EINVAL, "nsteps must be >= 0");
-    if (nsteps == 0) return MPDATA_OK;
-    hipError_t e = c->p.dtype == MPDATA_FP64 ? run_steps<double>(c, nsteps)
-                                             : run_steps<float>(c, nsteps);
-    if (e != hipSuccess) return hip_fail(c, e, "step launch");
-    c->steps += nsteps;
-    return MPDATA_OK;
+    const int rc = engine_step(c->e, nsteps);
+    if (rc == MPDATA_OK) c->steps += nsteps;
+    return rc;
 }
 
 int mpdata_mass(mpdata_ctx *c, double *out)
 {
-    if (!c || !out) return c ? fail(c, MPDATA_EINVAL, "out is NULL") : MPDATA_EINVAL;
-    double *parts = (double *)(c->ws + c->lay.partials);
-    double *res = (double *)(c->ws + c->lay.result);
-    const size_t n = cells_of(&c->p);
-    hipError_t e;
-    if (c->p.dtype == MPDATA_FP64)
-        e = mpd::launch_mass<double>((const double *)c->psi, (const double *)c->h, n, parts,
-                                     kMassParts, res, c->stream);
-    else
-        e = mpd::launch_mass<float>((const float *)c->psi, (const float *)c->h, n, parts,
-                                    kMassParts, res, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "mass launch");
-    double r[2];
-    e = hipMemcpyAsync(r, res, sizeof(r), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "mass readback");
-    *out = r[0];
-    if (!isfinite(r[0])) return fail(c, MPDATA_ENONFINITE, "psi holds NaN or Inf");
-    return MPDATA_OK;
+    if (!c) return MPDATA_EINVAL;
+    if (!out) return fail_to(c->e.err, MPDATA_EINVAL, "out is NULL");
+    return engine_mass(c->e, 0, out);
 }
 
 int mpdata_get_psi(mpdata_ctx *c, void *dst)
 {
     if (!c) return MPDATA_EINVAL;
-    if (!dst) return fail(c, MPDATA_EINVAL, "dst is NULL");
-    hipError_t e = hipMemcpyAsync(dst, c->psi, cells_of(&c->p) * word_of(&c->p),
-                                  hipMemcpyDeviceToDevice, c->stream);
-    return e == hipSuccess ? MPDATA_OK : hip_fail(c, e, "get_psi");
+    if (!dst) return fail_to(c->e.err, MPDATA_EINVAL, "dst is NULL");
+    hipError_t r = hipMemcpyAsync(dst, c->e.grids[0].psi[0], cells_of(&c->e.params[0]) * word_of(&c->e.params[0]),
+                                  hipMemcpyDeviceToDevice, c->e.stream);
+    return r == hipSuccess ? MPDATA_OK
+                           : fail_to(c->e.err, MPDATA_EDEVICE, "get_psi: %s", hipGetErrorString(r));
 }
 
 int mpdata_set_psi(mpdata_ctx *c, const void *src)
 {
     if (!c) return MPDATA_EINVAL;
-    if (!src) return fail(c, MPDATA_EINVAL, "src is NULL");
-    hipError_t e = hipMemcpyAsync(c->psi, src, cells_of(&c->p) * word_of(&c->p),
-                                  hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "set_psi");
+    if (!src) return fail_to(c->e.err, MPDATA_EINVAL, "src is NULL");
+    hipError_t r = hipMemcpyAsync(c->e.grids[0].psi[0], src, cells_of(&c->e.params[0]) * word_of(&c->e.params[0]),
+                                  hipMemcpyDeviceToDevice, c->e.stream);
+    if (r != hipSuccess) return fail_to(c->e.err, MPDATA_EDEVICE, "set_psi: %s", hipGetErrorString(r));
     c->steps = 0;
     return MPDATA_OK;
 }
@@ -282,14 +634,123 @@ int mpdata_set_psi(mpdata_ctx *c, const void *src)
 int mpdata_sync(mpdata_ctx *c)
 {
     if (!c) return MPDATA_EINVAL;
-    hipError_t e = hipStreamSynchronize(c->stream);
-    return e == hipSuccess ? MPDATA_OK : hip_fail(c, e, "hipStreamSynchronize");
+    hipError_t r = hipStreamSynchronize(c->e.stream);
+    return r == hipSuccess ? MPDATA_OK
+                           : fail_to(c->e.err, MPDATA_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(r));
 }
 
 int64_t mpdata_steps_done(const mpdata_ctx *c) { return c ? c->steps : -1; }
 
-void mpdata_destroy(mpdata_ctx *c) { delete c; }
+void mpdata_destroy(mpdata_ctx *c)
+{
+    if (!c) return;
+    engine_release(c->e);
+    delete c;
+}
 
-const char *mpdata_last_error(const mpdata_ctx *c) { return c ? c->err : g_create_err; }
+const char *mpdata_last_error(const mpdata_ctx *c) { return c ? c->e.err : g_create_err; }
+
+// ------------------------------------------------------------------ batches
+
+size_t mpdata_batch_workspace_bytes(int32_t n, const mpdata_params *params, int32_t max_segments,
+                                    int32_t max_wg)
+{
+    if (n < 1 || !params || max_segments < 0 || max_wg < 0) return 0;
+    for (int i = 0; i < n; ++i)
+        if (check_params(&params[i]) || params[i].iord != 2) return 0;
+    int nseg = 0, nwg = 0;
+    default_bounds(n, params, tile_of(&params[0]), &nseg, &nwg);
+    return workspace_for(n, params, std::max(nseg, (int)max_segments), std::max(nwg, (int)max_wg));
+}
+
+int mpdata_batch_default_plan_size(int32_t n, const mpdata_params *params, int32_t tile,
+                                   int32_t *nseg, int32_t *nwg)
+{
+    if (n < 1 || !params) return MPDATA_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (check_params(&params[i])) return MPDATA_EINVAL;
+    if (tile == 0) tile = tile_of(&params[0]);
+    if (tile < 1 || tile > mpdata_tile_count()) return MPDATA_EINVAL;
+    const int per = wg_per_cu(params[0].dtype, tile, params[0].bc == MPDATA_BC_OPEN, params[0].nonos != 0);
+    const int cus = device_cus();
+    if (per < 1 || cus < 1) return MPDATA_EDEVICE;
+    std::vector<mpdata_params> v(params, params + n);
+    std::vector<mpd::Segment> segs;
+    std::vector<int> wg;
+    default_plan(v, tile, per * cus, segs, wg);
+    if (nseg) *nseg = (int32_t)segs.size();
+    if (nwg) *nwg = (int32_t)wg.size() - 1;
+    return MPDATA_OK;
+}
+
+int mpdata_batch_create(int32_t n, const mpdata_params *params, void *const *psi,
+                        const void *const *u1, const void *const *u2, const void *const *u3,
+                        const void *const *h, void *workspace, size_t ws_bytes, void *stream,
+                        const mpdata_plan *plan, mpdata_batch **out)
+{
+    g_create_err[0] = 0;
+    if (!out) return fail_to(g_create_err, MPDATA_EINVAL, "out is NULL");
+    *out = nullptr;
+    mpdata_batch *b = new (std::nothrow) mpdata_batch;
+    if (!b) return fail_to(g_create_err, MPDATA_ENOMEM, "host allocation failed");
+    const int rc = engine_init(b->e, g_create_err, n, params, psi, u1, u2, u3, h, workspace,
+                               ws_bytes, stream, plan, true);
+    if (rc != MPDATA_OK) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return MPDATA_OK;
+}
+
+int mpdata_batch_step(mpdata_batch *b, int32_t nsteps)
+{
+    if (!b) return MPDATA_EINVAL;
+    return engine_step(b->e, nsteps);
+}
+
+int mpdata_batch_profile_step(mpdata_batch *b, int64_t *cycles_out, int32_t nseg)
+{
+    if (!b) return MPDATA_EINVAL;
+    Engine &e = b->e;
+    if (!cycles_out || nseg != e.nseg)
+        return fail_to(e.err, MPDATA_EINVAL, "cycles_out must hold the plan's %d segments", e.nseg);
+    long long *ticks = (long long *)(e.ws + e.lay.ticks);
+    hipError_t r = launch_one(e, 0, ticks);
+    if (r == hipSuccess)
+        r = e.dtype == MPDATA_FP32
+                ? mpd::launch_copy_back<float>((const mpd::GridDesc<float> *)(e.ws + e.lay.grids), e.ngrids, e.stream)
+                : mpd::launch_copy_back<double>((const mpd::GridDesc<double> *)(e.ws + e.lay.grids), e.ngrids, e.stream);
+    if (r == hipSuccess)
+        r = hipMemcpyAsync(cycles_out, ticks, (size_t)nseg * sizeof(long long), hipMemcpyDeviceToHost,
+                           e.stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(e.stream);
+    if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "profile step: %s", hipGetErrorString(r));
+    return MPDATA_OK;
+}
+
+int mpdata_batch_mass(mpdata_batch *b, int32_t i, double *out)
+{
+    if (!b) return MPDATA_EINVAL;
+    if (!out || i < 0 || i >= b->e.ngrids) return fail_to(b->e.err, MPDATA_EINVAL, "bad grid index or out");
+    return engine_mass(b->e, i, out);
+}
+
+int mpdata_batch_sync(mpdata_batch *b)
+{
+    if (!b) return MPDATA_EINVAL;
+    hipError_t r = hipStreamSynchronize(b->e.stream);
+    return r == hipSuccess ? MPDATA_OK
+                           : fail_to(b->e.err, MPDATA_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(r));
+}
+
+void mpdata_batch_destroy(mpdata_batch *b)
+{
+    if (!b) return;
+    engine_release(b->e);
+    delete b;
+}
+
+const char *mpdata_batch_last_error(const mpdata_batch *b) { return b ? b->e.err : g_create_err; }
 
 }  // extern "C"

@@ -6,14 +6,18 @@
 
 namespace mpd {
 
-// Arguments of one step launch: psi_in -> psi_out over an nx*ny*nz grid.
-template <typename T> struct StepArgs {
-    const T *psi_in;
-    T *psi_out;
+// One grid of a launch: its read-only inputs and the two psi buffers of the
+// time loop (a step reads psi[flip] and writes psi[1 - flip]).
+template <typename T> struct GridDesc {
     const T *u1, *u2, *u3, *h;
-    int nx, ny, nz;
-    int zlen;    // planes per z-chunk (one workgroup marches one chunk)
-    double eps;
+    T *psi[2];
+    int nx, ny, nz, pad;
+};
+
+// A piece of work of the persistent step kernel: output tile (tx, ty) of a
+// grid over the planes [z0, z1).
+struct Segment {
+    int grid, tx, ty, z0, z1, pad0, pad1, pad2;
 };
 
 // x-y region of one workgroup (output tile = region minus a 2-cell halo)
@@ -23,9 +27,29 @@ struct TileShape {
 
 const TileShape *tile_shapes(int *count);
 
+// The persistent fused step kernel for (T, tile id, open, nonos), as a
+// function pointer (for graph nodes and occupancy queries).
+template <typename T> const void *step_kernel_ptr(int tile, bool open, bool nonos);
+
 template <typename T>
-hipError_t launch_step(const StepArgs<T> &a, int tile, int iord, bool open, bool nonos,
-                       hipStream_t s);
+hipError_t launch_persistent(const GridDesc<T> *grids, const Segment *segs, const int *wg_begin,
+                             int nwg, int tile, bool open, bool nonos, int flip, double eps,
+                             long long *seg_ticks, hipStream_t s);
+
+// Donor-cell pass only (iord 1), one grid: psi[flip] -> psi[1 - flip].
+template <typename T> struct DonorArgs {
+    const T *psi_in;
+    T *psi_out;
+    const T *u1, *u2, *u3, *h;
+    int nx, ny, nz;
+};
+template <typename T> hipError_t launch_donor(const DonorArgs<T> &a, bool open, hipStream_t s);
+template <typename T> const void *donor_kernel_ptr(bool open);
+
+// psi of every grid of a launch copied from psi[1] back to psi[0].
+template <typename T> const void *copy_back_kernel_ptr();
+template <typename T>
+hipError_t launch_copy_back(const GridDesc<T> *grids, int ngrids, hipStream_t s);
 
 template <typename T>
 hipError_t launch_mass(const T *psi, const T *h, size_t n, double *partials, int nparts,

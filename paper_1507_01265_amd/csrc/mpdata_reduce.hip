@@ -1,0 +1,209 @@
+// mpdata_reduce.hip -- gfx950 kernels of the mass check and of the input
+// validation of libmpdata.  Compiled with full IEEE semantics (NaN and Inf
+// are detected here), unlike the step kernels.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mpdata_kernels.h"
+
+namespace mpd {
+
+// ============================================================ mass reduction
+// Double-double accumulation (TwoProduct by FMA, Knuth TwoSum), a wave64
+// butterfly with double-double adds, a block combine in LDS, one partial per
+// block; the final pass sums the partials in a fixed order.
+
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ DD two_sum(double a, double b)
+{
+#pragma clang fp contract(off)
+    double s = a + b;
+    double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+
+__device__ __forceinline__ DD dd_add(DD a, DD b)
+{
+#pragma clang fp contract(off)
+    DD s = two_sum(a.hi, b.hi);
+    double lo = s.lo + (a.lo + b.lo);
+    double hi = s.hi + lo;
+    return {hi, lo - (hi - s.hi)};
+}
+
+__device__ __forceinline__ DD dd_add_prod(DD acc, double x, double y)
+{
+#pragma clang fp contract(off)
+    double p = x * y;
+    double e = fma(x, y, -p);
+    DD s = two_sum(acc.hi, p);
+    return {s.hi, acc.lo + (s.lo + e)};
+}
+
+__device__ __forceinline__ DD wave_reduce(DD v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        DD o{__shfl_xor(v.hi, m, 64), __shfl_xor(v.lo, m, 64)};
+        v = dd_add(v, o);
+    }
+    return v;
+}
+
+__device__ __forceinline__ DD block_reduce(DD v)
+{
+    __shared__ double s_hi[16], s_lo[16];
+    v = wave_reduce(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+        s_hi[w] = v.hi;
+        s_lo[w] = v.lo;
+    }
+    __syncthreads();
+    DD r{0.0, 0.0};
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) r = dd_add(r, DD{s_hi[i], s_lo[i]});
+    }
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void mass_partials(const T *__restrict__ psi,
+                                                     const T *__restrict__ h, size_t n,
+                                                     double *__restrict__ partials)
+{
+    DD acc{0.0, 0.0};
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (size_t)gridDim.x * blockDim.x)
+        acc = dd_add_prod(acc, double(h[c]), double(psi[c]));
+    DD r = block_reduce(acc);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = r.hi;
+        partials[2 * blockIdx.x + 1] = r.lo;
+    }
+}
+
+__global__ __launch_bounds__(256) void mass_final(const double *__restrict__ partials, int nparts,
+                                                  double *__restrict__ result)
+{
+    DD acc{0.0, 0.0};
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x)
+        acc = dd_add(acc, DD{partials[2 * i], partials[2 * i + 1]});
+    DD r = block_reduce(acc);
+    if (threadIdx.x == 0) {
+        result[0] = r.hi + r.lo;
+        result[1] = r.lo;
+    }
+}
+
+// ================================================================ validation
+
+__device__ __forceinline__ bool same_bits(double a, double b)
+{
+    return __double_as_longlong(a) == __double_as_longlong(b);
+}
+
+__device__ __forceinline__ bool same_bits(float a, float b)
+{
+    return __float_as_int(a) == __float_as_int(b);
+}
+
+// flags[0]: count of h <= 0 or non-finite; flags[1]: count of periodic face
+// pairs (face n vs face 0) that differ bitwise.
+
+template <typename T>
+__global__ __launch_bounds__(256) void validate(const T *__restrict__ h, const T *__restrict__ u1,
+                                                const T *__restrict__ u2, const T *__restrict__ u3,
+                                                int nx, int ny, int nz, int periodic,
+                                                unsigned int *__restrict__ flags)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    unsigned int bad_h = 0, bad_f = 0;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (size_t)gridDim.x * blockDim.x) {
+        const T v = h[c];
+        if (!(v > T(0)) || !isfinite(v)) ++bad_h;
+        if (periodic) {
+            const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+            if (i == 0) {
+                const size_t r = ((size_t)k * ny + j) * (nx + 1);
+                if (!same_bits(u1[r], u1[r + nx])) ++bad_f;
+            }
+            if (j == 0) {
+                const size_t r0 = ((size_t)k * (ny + 1)) * nx + i;
+                if (!same_bits(u2[r0], u2[r0 + (size_t)ny * nx])) ++bad_f;
+            }
+            if (k == 0) {
+                const size_t r0 = (size_t)j * nx + i;
+                if (!same_bits(u3[r0], u3[r0 + (size_t)nz * ny * nx])) ++bad_f;
+            }
+        }
+    }
+    if (bad_h) atomicAdd(&flags[0], bad_h);
+    if (bad_f) atomicAdd(&flags[1], bad_f);
+}
+
+// ================================================================ copy back
+// psi[1] -> psi[0] for every grid of a launch (ends an odd number of steps);
+// one workgroup row per grid.
+
+template <typename T>
+__global__ __launch_bounds__(256) void copy_back(const GridDesc<T> *__restrict__ grids)
+{
+    const GridDesc<T> g = grids[blockIdx.y];
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (size_t)gridDim.x * blockDim.x)
+        g.psi[0][c] = g.psi[1][c];
+}
+
+// ===================================================================== launch
+
+template <typename T> const void *copy_back_kernel_ptr() { return (const void *)copy_back<T>; }
+
+template <typename T> hipError_t launch_copy_back(const GridDesc<T> *grids, int ngrids, hipStream_t s)
+{
+    copy_back<T><<<dim3(1024, ngrids), 256, 0, s>>>(grids);
+    return hipGetLastError();
+}
+
+template const void *copy_back_kernel_ptr<double>();
+template const void *copy_back_kernel_ptr<float>();
+template hipError_t launch_copy_back<double>(const GridDesc<double> *, int, hipStream_t);
+template hipError_t launch_copy_back<float>(const GridDesc<float> *, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_mass(const T *psi, const T *h, size_t n, double *partials, int nparts,
+                       double *result, hipStream_t s)
+{
+    mass_partials<T><<<nparts, 256, 0, s>>>(psi, h, n, partials);
+    mass_final<<<1, 256, 0, s>>>(partials, nparts, result);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_validate(const T *h, const T *u1, const T *u2, const T *u3, int nx, int ny,
+                           int nz, int periodic, unsigned int *flags, hipStream_t s)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    validate<T><<<blocks, 256, 0, s>>>(h, u1, u2, u3, nx, ny, nz, periodic, flags);
+    return hipGetLastError();
+}
+
+template hipError_t launch_mass<double>(const double *, const double *, size_t, double *, int,
+                                        double *, hipStream_t);
+template hipError_t launch_mass<float>(const float *, const float *, size_t, double *, int,
+                                       double *, hipStream_t);
+template hipError_t launch_validate<double>(const double *, const double *, const double *,
+                                            const double *, int, int, int, int, unsigned int *,
+                                            hipStream_t);
+template hipError_t launch_validate<float>(const float *, const float *, const float *,
+                                           const float *, int, int, int, int, unsigned int *,
+                                           hipStream_t);
+
+}  // namespace mpd

@@ -1,0 +1,584 @@
+// mpdata_step.hip -- the fused MPDATA time-step kernel for gfx950.
+//
+// One time step (paper, section 5.2: a chain of dependent stencil stages
+// turning five input matrices into one output; the equations are those of
+// the MPDATA literature the paper cites: donor-cell pass and antidiffusive
+// pseudo-velocities of Smolarkiewicz 1984, non-oscillatory limiter of
+// Smolarkiewicz & Grabowski 1990, density weighting of Smolarkiewicz &
+// Margolin 1998):
+//   S1+S2  psi1 = psi - sum_d dF_d / h,  F = donor(psi_lo, psi_hi, U)
+//   S3     V on every face from psi1, U, h (A ratio, cross terms B, G)
+//   S4     mx, mn = max/min of psi and psi1 over the 7-point neighbourhood
+//   S5     beta_up = (mx - psi1) h / (IN + eps), beta_dn = (psi1 - mn) h / (OUT + eps)
+//   S6     Vt = min(1, bdn_lo, bup_hi) pos(V) + min(1, bup_lo, bdn_hi) neg(V)
+//   S7     psi_out = psi1 - sum_d dFC_d / h,  FC = donor(psi1_lo, psi1_hi, Vt)
+//
+// Fusion (the paper's (3+1)D decomposition, section 5.3: tile the domain
+// and fuse the stage loop so intermediates stay on chip, paying with halo
+// recompute), recast for CDNA:
+//  * a workgroup owns an RX x RY region of x-y columns (its output tile plus
+//    a 2-cell halo) and marches along z through a chunk of planes;
+//  * a thread owns one column and keeps its z-history in registers;
+//    in-plane neighbours are exchanged through LDS planes padded by one
+//    cell on every side, so neighbour offsets are compile-time constants;
+//  * the stage pipeline is skewed in z: iteration t computes psi1 at plane
+//    t, V, the bounds and the limiter factors at plane t-1 (and V3 on face
+//    t), the limited fluxes and the output at plane t-2; the march is
+//    unrolled by three so the three psi1 planes sit in fixed LDS slots;
+//  * psi^n and u3 of plane t+2 and the other inputs of plane t+1 are
+//    prefetched into registers.
+// Only psi^{n+1} is written to HBM: 5 array reads + 1 write per cell-step.
+//
+// This translation unit is compiled without NaN semantics (finite inputs
+// are a precondition of the step; mpdata_mass reports NaN/Inf in psi).
+//
+// Boundaries: periodic wraps cell indices (face n == face 0); open is
+// zero-gradient (ghost cells equal the nearest interior cell; reads of
+// cell-centred neighbours at the domain edge are redirected to the cell
+// itself) with zero antidiffusive velocity on boundary-normal faces.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "mpdata_kernels.h"
+
+namespace mpd {
+
+// ------------------------------------------------------------ index helpers
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ int clampi(int i, int lo, int hi)
+{
+    return i < lo ? lo : (i > hi ? hi : i);
+}
+
+template <bool OPEN> __device__ __forceinline__ int cell_of(int i, int n)
+{
+    return OPEN ? clampi(i, 0, n - 1) : wrapi(i, n);
+}
+
+// face below / above position i along an axis of n cells (face index 0..n)
+template <bool OPEN> __device__ __forceinline__ int face_lo(int i, int n)
+{
+    return OPEN ? clampi(i, 0, n) : wrapi(i, n);
+}
+
+template <bool OPEN> __device__ __forceinline__ int face_hi(int i, int n)
+{
+    return OPEN ? clampi(i + 1, 0, n) : wrapi(i, n) + 1;
+}
+
+// ---------------------------------------------------------------- arithmetic
+
+template <typename T> __device__ __forceinline__ T pos(T x) { return fmax(x, T(0)); }
+template <typename T> __device__ __forceinline__ T neg(T x) { return fmin(x, T(0)); }
+
+// donor-cell flux through a face with lower value l, upper value r
+template <typename T> __device__ __forceinline__ T donor(T l, T r, T c)
+{
+    return pos(c) * l + neg(c) * r;
+}
+
+// Reciprocal by the hardware estimate refined with Newton-Raphson steps
+// r <- r + r (1 - x r) (two for FP64, one for FP32), and a quotient with one
+// residual correction q <- q + r (n - d q).  Accurate to about one unit in
+// the last place for the positive, normal operands used here.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ float rcp_nr(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
+template <typename T> __device__ __forceinline__ T div_nr(T n, T d)
+{
+    const T r = rcp_nr(d);
+    const T q = n * r;
+    return fma(fma(-d, q, n), r, q);
+}
+
+template <typename T> struct Tiny;
+template <> struct Tiny<double> { static constexpr double v = 2.2250738585072014e-308; };
+template <> struct Tiny<float> { static constexpr float v = 1.17549435e-38f; };
+
+// Antidiffusive pseudo-velocity on a face between lower cell a and upper
+// cell b (face-normal Courant number U, hs = h_a + h_b; us, ut = sums of the
+// four transverse Courant numbers of a and b along the transverse axes s
+// and t; s_hi = psi1_b,s+1 + psi1_a,s+1 and s_lo likewise one cell down, the
+// same for t).  The definition
+//   V = (|U| - U^2/G) A - (U/G) (Us Bs + Ut Bt),  G = hs/2,
+//   A = (pb - pa)/(pb + pa + eps),  Bs = (s_hi - s_lo)/(2 (s_hi + s_lo + eps)),
+//   Us = us/4 (and t likewise)
+// is evaluated over one common denominator, so a face costs one division:
+//   V = [(|U| hs - 2U^2) nA dBs dBt - (U dA/4)(us nBs dBt + ut nBt dBs)]
+//       / (hs dA dBs dBt).
+// A denominator below the smallest normal number (all neighbouring psi1
+// within eps of zero, possible in FP32 only) gives V = 0.
+template <typename T>
+__device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi, T s_lo, T ut,
+                                             T t_hi, T t_lo, T eps)
+{
+    const T nA = pb - pa, dA = (pb + pa) + eps;
+    const T nBs = s_hi - s_lo, dBs = (s_hi + s_lo) + eps;
+    const T nBt = t_hi - t_lo, dBt = (t_hi + t_lo) + eps;
+    const T P = dBs * dBt;
+    const T c = fabs(U) * hs - T(2) * (U * U);
+    const T cross = (us * nBs) * dBt + (ut * nBt) * dBs;
+    const T num = (c * nA) * P - (T(0.25) * U * dA) * cross;
+    const T den = (hs * dA) * P;
+    return den >= Tiny<T>::v ? div_nr(num, den) : T(0);
+}
+
+// Limited pseudo-velocity; the factors are in limiter precision (double).
+template <typename T>
+__device__ __forceinline__ T limited(T v, double bup_a, double bdn_a, double bup_b, double bdn_b)
+{
+    const T cp = T(fmin(1.0, fmin(bdn_a, bup_b)));
+    const T cn = T(fmin(1.0, fmin(bup_a, bdn_b)));
+    return cp * pos(v) + cn * neg(v);
+}
+
+// Registers of one plane of a column: the Courant numbers of its x- and
+// y-faces and h (needed one iteration ahead) ...
+template <typename T> struct PlaneA {
+    T u1lo, u1hi, u2lo, u2hi, h;
+};
+// ... and psi^n, the Courant number of its lower z-face and the LDS ring of
+// psi^n (needed two iterations ahead).
+template <typename T> struct PlaneB {
+    T pn, u3lo, ringx, ringy;
+};
+
+// ================================================================ fused step
+
+// LDS planes of one workgroup (each padded by one cell on every side).
+template <typename T, int RX, int RY> struct Smem {
+    static constexpr int PX = RX + 2, PP = PX * (RY + 2);
+    T sP[PP];                            // psi^n plane t (its ring holds real data)
+    T sQ[3][PP];                         // psi1, planes t-2 .. t in fixed slots
+    T sC1[PP], sC2[PP], sC3[PP], sH[PP]; // Courant column sums, h: plane t-1
+    T sFA1[PP], sFA2[PP];                // antidiffusive donor fluxes, lower faces
+    double sBU[PP], sBD[PP];             // limiter factors, plane t-2
+    T sFC1[PP], sFC2[PP];                // corrective fluxes, lower faces
+};
+
+// One workgroup advances the output tile (tx, ty) of grid g through planes
+// [z0, z1): psi[flip] -> psi[1 - flip].
+template <typename T, int RX, int RY, bool OPEN, bool NONOS>
+__device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, int ty, int z0,
+                                      int z1, double eps_d, Smem<T, RX, RY> &sm)
+{
+    using L = double;  // limiter precision (both variants)
+    constexpr int TX = RX - 4, TY = RY - 4;
+    constexpr int PX = RX + 2;           // padded row pitch of every LDS plane
+    constexpr int XM = -1, XP = 1, YM = -PX, YP = PX;
+    T *__restrict__ sP = sm.sP;
+    auto &sQ = sm.sQ;
+    T *__restrict__ sC1 = sm.sC1, *__restrict__ sC2 = sm.sC2, *__restrict__ sC3 = sm.sC3;
+    T *__restrict__ sH = sm.sH, *__restrict__ sFA1 = sm.sFA1, *__restrict__ sFA2 = sm.sFA2;
+    L *__restrict__ sBU = sm.sBU, *__restrict__ sBD = sm.sBD;
+    T *__restrict__ sFC1 = sm.sFC1, *__restrict__ sFC2 = sm.sFC2;
+
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const T eps = T(eps_d);
+    const L eps_l = eps_d;
+    const T *__restrict__ psi_in = g.psi[flip];
+    T *__restrict__ psi_out = g.psi[1 - flip];
+
+    const int tid = threadIdx.x;
+    const int lx = tid % RX, ly = tid / RX;
+    const int gx = tx * TX - 2 + lx;
+    const int gy = ty * TY - 2 + ly;
+    const int q = (ly + 1) * PX + lx + 1;
+
+    // in-plane offsets into the global arrays
+    const int cx = cell_of<OPEN>(gx, nx), cy = cell_of<OPEN>(gy, ny);
+    const size_t pc_cells = (size_t)nx * ny;
+    const size_t pc_u1 = (size_t)(nx + 1) * ny;
+    const size_t pc_u2 = (size_t)nx * (ny + 1);
+    const unsigned o_c = cy * nx + cx;
+    const unsigned o_u1lo = cy * (nx + 1) + face_lo<OPEN>(gx, nx);
+    const unsigned o_u1hi = cy * (nx + 1) + face_hi<OPEN>(gx, nx);
+    const unsigned o_u2lo = face_lo<OPEN>(gy, ny) * nx + cx;
+    const unsigned o_u2hi = face_hi<OPEN>(gy, ny) * nx + cx;
+    const bool has_rx = (lx == 0) || (lx == RX - 1);
+    const bool has_ry = (ly == 0) || (ly == RY - 1);
+    const unsigned o_rx = cy * nx + cell_of<OPEN>(lx == 0 ? gx - 1 : gx + 1, nx);
+    const unsigned o_ry = cell_of<OPEN>(ly == 0 ? gy - 1 : gy + 1, ny) * nx + cx;
+    const int p_rx = q + (lx == 0 ? XM : XP);
+    const int p_ry = q + (ly == 0 ? YM : YP);
+
+    // cell-centred neighbour offsets: at an open boundary a read of the cell
+    // beyond it is redirected to the cell itself (zero gradient)
+    const int cxm = (OPEN && gx <= 0) ? 0 : XM;
+    const int cxp = (OPEN && gx >= nx - 1) ? 0 : XP;
+    const int cym = (OPEN && gy <= 0) ? 0 : YM;
+    const int cyp = (OPEN && gy >= ny - 1) ? 0 : YP;
+
+    // boundary-normal faces of an open domain carry no antidiffusive flux
+    const bool zero_v1 = OPEN && (gx <= 0 || gx >= nx);
+    const bool zero_v2 = OPEN && (gy <= 0 || gy >= ny);
+    const bool is_out = lx >= 2 && lx < RX - 2 && ly >= 2 && ly < RY - 2 && gx < nx && gy < ny;
+
+    // plane index of position t along z: wrapped (periodic) or clamped (open);
+    // the march advances it by one per iteration without a division
+    auto plane_of = [&](int t) { return cell_of<OPEN>(t, nz); };
+    auto zface_of = [&](int t) { return face_lo<OPEN>(t, nz); };
+    auto next_plane = [&](int k, int t_next) {
+        if (OPEN) return clampi(t_next, 0, nz - 1);
+        return k + 1 == nz ? 0 : k + 1;
+    };
+    auto load_a = [&](int k, PlaneA<T> &r) {
+        const T *__restrict__ hp = g.h + (size_t)k * pc_cells;
+        const T *__restrict__ u1p = g.u1 + (size_t)k * pc_u1;
+        const T *__restrict__ u2p = g.u2 + (size_t)k * pc_u2;
+        r.h = hp[o_c];
+        r.u1lo = u1p[o_u1lo];
+        r.u1hi = u1p[o_u1hi];
+        r.u2lo = u2p[o_u2lo];
+        r.u2hi = u2p[o_u2hi];
+    };
+    auto load_b = [&](int k, int kf, PlaneB<T> &r) {
+        const T *__restrict__ pp = psi_in + (size_t)k * pc_cells;
+        const T *__restrict__ u3p = g.u3 + (size_t)kf * pc_cells;
+        r.pn = pp[o_c];
+        r.u3lo = u3p[o_c];
+        r.ringx = has_rx ? pp[o_rx] : T(0);
+        r.ringy = has_ry ? pp[o_ry] : T(0);
+    };
+    auto store_ring = [&](const PlaneB<T> &r) {
+        sP[q] = r.pn;
+        if (has_rx) sP[p_rx] = r.ringx;
+        if (has_ry) sP[p_ry] = r.ringy;
+    };
+
+    const int t0 = z0 - 2, tend = z1 + 1;
+    // the march runs a multiple of three iterations; iterations past tend
+    // only reload valid planes and store nothing
+    const int tstop = t0 + ((tend - t0 + 1 + 2) / 3) * 3 - 1;
+    PlaneA<T> curA, nxA;
+    PlaneB<T> cur, nx1, nx2;
+    int ka = plane_of(t0 + 1);                     // plane of t+1 (load_a)
+    int kb = plane_of(t0 + 2);                     // plane of t+2 (load_b)
+    load_a(plane_of(t0), curA);
+    load_b(plane_of(t0), zface_of(t0), cur);
+    load_b(ka, zface_of(t0 + 1), nx1);
+    const T pn_prev = psi_in[(size_t)plane_of(t0 - 1) * pc_cells + o_c];
+    store_ring(cur);
+
+    // z-history of the column
+    T f3_c = donor(pn_prev, cur.pn, cur.u3lo);  // psi^n flux, face t
+    T pn_m1 = pn_prev, pn_m2 = T(0);
+    T pmx_m1 = T(0), pmn_m1 = T(0);             // in-plane 5-point max/min of psi^n(t-1)
+    T u1_m1 = T(0), u2_m1 = T(0);               // lower-face Courant, plane t-1
+    T rh_m1 = T(1), rh_m2 = T(1);               // 1/h of planes t-1, t-2
+    T v1_m2 = T(0), v2_m2 = T(0), v3_m1 = T(0); // V at plane t-2, V3 at face t-1
+    T fa3_m1 = T(0);                            // antidiffusive flux, face t-1
+    L bu_m2 = 1.0, bd_m2 = 1.0;                 // limiter factors, plane t-2
+    T fc3_m2 = T(0);                            // corrective flux, face t-2
+
+    auto iter = [&](const int t, auto slot) {
+        constexpr int s0 = decltype(slot)::value;           // slot of plane t
+        constexpr int s1 = (s0 + 2) % 3, s2 = (s0 + 1) % 3; // planes t-1, t-2
+        load_a(ka, nxA);
+        load_b(kb, OPEN ? zface_of(t + 2) : kb, nx2);
+        ka = kb;
+        kb = next_plane(kb, t + 3);
+        __syncthreads();  // (B) psi^n(t), sums/h of t-1 and beta of t-2 are visible
+        // own-column values of planes t-1 and t-2 that already sit in LDS
+        const T p1_m1 = sQ[s1][q], p1_m2 = sQ[s2][q];
+        const T c1_m1 = sC1[q], c2_m1 = sC2[q], c3_m1 = sC3[q], h_m1 = sH[q];
+
+        // ---- S1+S2 at plane t
+        const T pL = sP[q + cxm], pR = sP[q + cxp];
+        const T pD = sP[q + cym], pU = sP[q + cyp];
+        const T f1lo = donor(pL, cur.pn, curA.u1lo), f1hi = donor(cur.pn, pR, curA.u1hi);
+        const T f2lo = donor(pD, cur.pn, curA.u2lo), f2hi = donor(cur.pn, pU, curA.u2hi);
+        const T f3hi = donor(cur.pn, nx1.pn, nx1.u3lo);
+        const T rh_c = rcp_nr(curA.h);
+        const T p1_c = cur.pn - (((f1hi - f1lo) + (f2hi - f2lo)) + (f3hi - f3_c)) * rh_c;
+        const T pmx_c = fmax(fmax(fmax(pL, pR), fmax(pD, pU)), cur.pn);
+        const T pmn_c = fmin(fmin(fmin(pL, pR), fmin(pD, pU)), cur.pn);
+        sQ[s0][q] = p1_c;
+        const T c1_c = curA.u1lo + curA.u1hi;
+        const T c2_c = curA.u2lo + curA.u2hi;
+        const T c3_c = cur.u3lo + nx1.u3lo;
+        __syncthreads();  // (D) psi1(t) visible
+
+        T v1, v2, v3, fa3_c = T(0);
+        T mx = T(0), mn = T(0);
+        {
+            // ---- S3 at plane p = t-1 (lower x- and y-faces) and on face t
+            const int p = t - 1;
+            const bool clo = OPEN && p <= 0, chi = OPEN && p >= nz - 1;
+            const T *Qc = sQ[s1];
+            const T *Qb = sQ[s0];
+            const T *Qlo = clo ? sQ[s1] : sQ[s2];
+            const T *Qhi = chi ? sQ[s1] : sQ[s0];
+            const T p1_lo = clo ? p1_m1 : p1_m2;
+            const T p1_hi = chi ? p1_m1 : p1_c;
+
+            const T qa = Qc[q + XM];  // cell a of the lower x-face
+            const T qd = Qc[q + YM];  // cell a of the lower y-face
+            const T qyp_ = Qc[q + cyp], qym_ = Qc[q + cym];
+            const T qxp_ = Qc[q + cxp], qxm_ = Qc[q + cxm];
+            // x-face between a = (lx-1) and b = own; transverse axes y then z
+            v1 = pseudo_velocity(u1_m1, sH[q + XM] + h_m1, qa, p1_m1, sC2[q + XM] + c2_m1,
+                                 qyp_ + Qc[q + XM + cyp], qym_ + Qc[q + XM + cym],
+                                 sC3[q + XM] + c3_m1, p1_hi + Qhi[q + XM], p1_lo + Qlo[q + XM],
+                                 eps);
+            if (zero_v1) v1 = T(0);
+            // y-face between a = (ly-1) and b = own; transverse axes z then x
+            v2 = pseudo_velocity(u2_m1, sH[q + YM] + h_m1, qd, p1_m1, sC3[q + YM] + c3_m1,
+                                 p1_hi + Qhi[q + YM], p1_lo + Qlo[q + YM], sC1[q + YM] + c1_m1,
+                                 qxp_ + Qc[q + YM + cxp], qxm_ + Qc[q + YM + cxm], eps);
+            if (zero_v2) v2 = T(0);
+            // z-face t between a = plane t-1 and b = plane t; transverse x then y
+            v3 = pseudo_velocity(cur.u3lo, h_m1 + curA.h, p1_m1, p1_c, c1_m1 + c1_c,
+                                 Qb[q + cxp] + qxp_, Qb[q + cxm] + qxm_, c2_m1 + c2_c,
+                                 Qb[q + cyp] + qyp_, Qb[q + cym] + qym_, eps);
+            if (OPEN && (t <= 0 || t >= nz)) v3 = T(0);
+            if (NONOS) {
+                // ---- S4 bounds at plane p
+                const T pn_lo = clo ? pn_m1 : pn_m2, pn_hi = chi ? pn_m1 : cur.pn;
+                mx = fmax(fmax(fmax(pmx_m1, fmax(qxm_, qxp_)), fmax(fmax(qym_, qyp_), p1_m1)),
+                          fmax(fmax(pn_lo, pn_hi), fmax(p1_lo, p1_hi)));
+                mn = fmin(fmin(fmin(pmn_m1, fmin(qxm_, qxp_)), fmin(fmin(qym_, qyp_), p1_m1)),
+                          fmin(fmin(pn_lo, pn_hi), fmin(p1_lo, p1_hi)));
+                sFA1[q] = donor(qa, p1_m1, v1);
+                sFA2[q] = donor(qd, p1_m1, v2);
+                fa3_c = donor(p1_m1, p1_c, v3);
+            }
+        }
+        __syncthreads();  // (F) antidiffusive fluxes visible
+
+        L bu_m1 = 1.0, bd_m1 = 1.0;
+        if (NONOS) {
+            // ---- S5 limiter factors at plane t-1
+            const L x_lo = L(sFA1[q]), x_hi = L(sFA1[q + XP]);
+            const L y_lo = L(sFA2[q]), y_hi = L(sFA2[q + YP]);
+            const L z_lo = L(fa3_m1), z_hi = L(fa3_c);
+            const L in = ((pos(x_lo) - neg(x_hi)) + (pos(y_lo) - neg(y_hi))) + (pos(z_lo) - neg(z_hi));
+            const L ou = ((pos(x_hi) - neg(x_lo)) + (pos(y_hi) - neg(y_lo))) + (pos(z_hi) - neg(z_lo));
+            // beta_up = (mx - psi1) h / (IN + eps), beta_dn = (psi1 - mn) h / (OUT + eps),
+            // over the common denominator (IN + eps)(OUT + eps)
+            const L din = in + eps_l, dou = ou + eps_l;
+            const L r = rcp_nr(din * dou) * L(h_m1);
+            bu_m1 = ((L(mx) - L(p1_m1)) * dou) * r;
+            bd_m1 = ((L(p1_m1) - L(mn)) * din) * r;
+        }
+
+        T fc3_m1;
+        {
+            // ---- S6 + corrective fluxes at plane r = t-2 (lower faces) and on face t-1
+            const T *Qr = sQ[s2];
+            T vt1 = v1_m2, vt2 = v2_m2, vt3 = v3_m1;
+            if (NONOS) {
+                vt1 = limited(v1_m2, sBU[q + XM], sBD[q + XM], bu_m2, bd_m2);
+                vt2 = limited(v2_m2, sBU[q + YM], sBD[q + YM], bu_m2, bd_m2);
+                vt3 = limited(v3_m1, bu_m2, bd_m2, bu_m1, bd_m1);
+            }
+            if (zero_v1) vt1 = T(0);
+            if (zero_v2) vt2 = T(0);
+            if (OPEN && (t - 1 <= 0 || t - 1 >= nz)) vt3 = T(0);
+            sFC1[q] = donor(Qr[q + XM], p1_m2, vt1);
+            sFC2[q] = donor(Qr[q + YM], p1_m2, vt2);
+            fc3_m1 = donor(p1_m2, p1_m1, vt3);
+        }
+        __syncthreads();  // (J) corrective fluxes visible
+
+        {
+            // ---- S7 at plane r = t-2
+            const T fc1hi = sFC1[q + XP], fc2hi = sFC2[q + YP];
+            const T res = p1_m2 - (((fc1hi - sFC1[q]) + (fc2hi - sFC2[q])) + (fc3_m1 - fc3_m2)) * rh_m2;
+            if (is_out && t >= z0 + 2 && t <= tend) (psi_out + (size_t)(t - 2) * pc_cells)[o_c] = res;
+        }
+
+        // ---- hand the planes to the next iteration
+        if (NONOS) {
+            sBU[q] = bu_m1;
+            sBD[q] = bd_m1;
+        }
+        sC1[q] = c1_c;
+        sC2[q] = c2_c;
+        sC3[q] = c3_c;
+        sH[q] = curA.h;
+        store_ring(nx1);
+
+        pn_m2 = pn_m1;
+        pn_m1 = cur.pn;
+        pmx_m1 = pmx_c;
+        pmn_m1 = pmn_c;
+        u1_m1 = curA.u1lo;
+        u2_m1 = curA.u2lo;
+        rh_m2 = rh_m1;
+        rh_m1 = rh_c;
+        f3_c = f3hi;
+        v1_m2 = v1;
+        v2_m2 = v2;
+        v3_m1 = v3;
+        fa3_m1 = fa3_c;
+        bu_m2 = bu_m1;
+        bd_m2 = bd_m1;
+        fc3_m2 = fc3_m1;
+        curA = nxA;
+        cur = nx1;
+        nx1 = nx2;
+    };
+
+    for (int t = t0; t <= tstop; t += 3) {
+        iter(t, std::integral_constant<int, 0>{});
+        iter(t + 1, std::integral_constant<int, 1>{});
+        iter(t + 2, std::integral_constant<int, 2>{});
+    }
+}
+
+// Persistent step kernel: workgroup b walks the segments [wg_begin[b],
+// wg_begin[b+1]) of the plan -- (grid, tile, z-range) pieces balanced over
+// the workgroups and grouped so that neighbouring tiles share an XCD -- and
+// advances each one time step.  With seg_ticks non-null the wall-clock
+// duration of every segment is recorded (the per-block speeds a plan tuner
+// measures while all workgroups run together).
+template <typename T, int RX, int RY, bool OPEN, bool NONOS>
+__global__ __launch_bounds__(RX * RY) void step_kernel(const GridDesc<T> *__restrict__ grids,
+                                                      const Segment *__restrict__ segs,
+                                                      const int *__restrict__ wg_begin, int flip,
+                                                      double eps, long long *__restrict__ seg_ticks)
+{
+    __shared__ Smem<T, RX, RY> sm;
+    // Every LDS plane starts at zero, so values computed from not-yet-written
+    // slots in the first iterations of a march stay finite (they never reach
+    // an output).
+    for (int i = threadIdx.x; i < Smem<T, RX, RY>::PP; i += RX * RY) {
+        sm.sP[i] = T(0);
+        sm.sQ[0][i] = sm.sQ[1][i] = sm.sQ[2][i] = T(0);
+        sm.sC1[i] = sm.sC2[i] = sm.sC3[i] = sm.sH[i] = T(0);
+        sm.sFA1[i] = sm.sFA2[i] = sm.sFC1[i] = sm.sFC2[i] = T(0);
+        sm.sBU[i] = sm.sBD[i] = 1.0;
+    }
+    __syncthreads();
+    const int b = wg_begin[blockIdx.x], e = wg_begin[blockIdx.x + 1];
+    for (int s = b; s < e; ++s) {
+        const Segment sg = segs[s];
+        const long long t_start = seg_ticks ? (long long)wall_clock64() : 0;
+        march<T, RX, RY, OPEN, NONOS>(grids[sg.grid], flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+        __syncthreads();
+        // optional per-segment duration (workgroup-uniform; one lane stores)
+        if (seg_ticks && threadIdx.x == 0) seg_ticks[s] = (long long)wall_clock64() - t_start;
+    }
+}
+
+// ======================================================= donor cell (iord 1)
+
+template <typename T, bool OPEN>
+__global__ __launch_bounds__(256) void step_donor(DonorArgs<T> a)
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const size_t n = (size_t)nx * ny * nz;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+        auto at = [&](int ii, int jj, int kk) {
+            return a.psi_in[((size_t)cell_of<OPEN>(kk, nz) * ny + cell_of<OPEN>(jj, ny)) * nx +
+                            cell_of<OPEN>(ii, nx)];
+        };
+        const T vc = a.psi_in[c];
+        const T f1lo = donor(at(i - 1, j, k), vc, a.u1[((size_t)k * ny + j) * (nx + 1) + i]);
+        const T f1hi = donor(vc, at(i + 1, j, k), a.u1[((size_t)k * ny + j) * (nx + 1) + i + 1]);
+        const T f2lo = donor(at(i, j - 1, k), vc, a.u2[((size_t)k * (ny + 1) + j) * nx + i]);
+        const T f2hi = donor(vc, at(i, j + 1, k), a.u2[((size_t)k * (ny + 1) + j + 1) * nx + i]);
+        const T f3lo = donor(at(i, j, k - 1), vc, a.u3[((size_t)k * ny + j) * nx + i]);
+        const T f3hi = donor(vc, at(i, j, k + 1), a.u3[((size_t)(k + 1) * ny + j) * nx + i]);
+        a.psi_out[c] = vc - (((f1hi - f1lo) + (f2hi - f2lo)) + (f3hi - f3lo)) * rcp_nr(a.h[c]);
+    }
+}
+
+// ===================================================================== launch
+
+const TileShape *tile_shapes(int *count)
+{
+    static const TileShape shapes[] = {
+        {64, 16}, {32, 32}, {64, 8}, {32, 16}, {32, 24},
+    };
+    *count = (int)(sizeof(shapes) / sizeof(shapes[0]));
+    return shapes;
+}
+
+template <typename T, int RX, int RY> static const void *pick(bool open, bool nonos)
+{
+    if (open)
+        return nonos ? (const void *)step_kernel<T, RX, RY, true, true>
+                     : (const void *)step_kernel<T, RX, RY, true, false>;
+    return nonos ? (const void *)step_kernel<T, RX, RY, false, true>
+                 : (const void *)step_kernel<T, RX, RY, false, false>;
+}
+
+template <typename T> const void *step_kernel_ptr(int tile, bool open, bool nonos)
+{
+    switch (tile) {
+    case 1: return pick<T, 64, 16>(open, nonos);
+    case 2: return pick<T, 32, 32>(open, nonos);
+    case 3: return pick<T, 64, 8>(open, nonos);
+    case 4: return pick<T, 32, 16>(open, nonos);
+    case 5: return pick<T, 32, 24>(open, nonos);
+    default: return nullptr;
+    }
+}
+
+template <typename T>
+hipError_t launch_persistent(const GridDesc<T> *grids, const Segment *segs, const int *wg_begin,
+                             int nwg, int tile, bool open, bool nonos, int flip, double eps,
+                             long long *seg_ticks, hipStream_t s)
+{
+    int count = 0;
+    const TileShape *sh = tile_shapes(&count);
+    const void *k = step_kernel_ptr<T>(tile, open, nonos);
+    if (!k || nwg < 1) return hipErrorInvalidValue;
+    void *args[] = {(void *)&grids, (void *)&segs, (void *)&wg_begin, (void *)&flip, (void *)&eps,
+                    (void *)&seg_ticks};
+    return hipLaunchKernel(k, dim3(nwg), dim3(sh[tile - 1].rx * sh[tile - 1].ry), args, 0, s);
+}
+
+template <typename T> const void *donor_kernel_ptr(bool open)
+{
+    return open ? (const void *)step_donor<T, true> : (const void *)step_donor<T, false>;
+}
+
+template <typename T> hipError_t launch_donor(const DonorArgs<T> &a, bool open, hipStream_t s)
+{
+    const size_t n = (size_t)a.nx * a.ny * a.nz;
+    const int blocks = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    if (open) step_donor<T, true><<<blocks, 256, 0, s>>>(a);
+    else step_donor<T, false><<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template const void *step_kernel_ptr<double>(int, bool, bool);
+template const void *step_kernel_ptr<float>(int, bool, bool);
+template hipError_t launch_persistent<double>(const GridDesc<double> *, const Segment *,
+                                              const int *, int, int, bool, bool, int, double,
+                                              long long *, hipStream_t);
+template hipError_t launch_persistent<float>(const GridDesc<float> *, const Segment *, const int *,
+                                             int, int, bool, bool, int, double, long long *,
+                                             hipStream_t);
+template const void *donor_kernel_ptr<double>(bool);
+template const void *donor_kernel_ptr<float>(bool);
+template hipError_t launch_donor<double>(const DonorArgs<double> &, bool, hipStream_t);
+template hipError_t launch_donor<float>(const DonorArgs<float> &, bool, hipStream_t);
+
+}  // namespace mpd

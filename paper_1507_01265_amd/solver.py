@@ -22,10 +22,12 @@ def _check_runtime():
         raise RuntimeError(f"more than one HIP runtime mapped: {mapped}")
 
 
-def make_params(shape, dtype=torch.float64, bc="periodic", iord=2, nonos=True, eps=1e-15, tile=0):
+def make_params(shape, dtype=torch.float64, bc="periodic", iord=2, nonos=True, eps=1e-15, tile=0,
+                graph=True):
     nz, ny, nx = shape
+    flags = 0 if graph else _lib.MPDATA_FLAG_NO_GRAPH
     return _lib.mpdata_params(nx, ny, nz, DTYPES[dtype], BC[bc], iord, int(bool(nonos)), tile,
-                              eps)
+                              flags, 0, eps)
 
 
 class Solver:
@@ -37,7 +39,7 @@ class Solver:
     """
 
     def __init__(self, psi, u1, u2, u3, h, *, bc="periodic", iord=2, nonos=True, eps=1e-15,
-                 tile=0, stream=None):
+                 tile=0, graph=True, stream=None):
         if not torch.cuda.is_available():
             raise RuntimeError("libmpdata needs a GPU")
         _lib.load()
@@ -52,7 +54,7 @@ class Solver:
                 raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {want[name]}")
             if not t.is_cuda or not t.is_contiguous() or t.dtype != psi.dtype:
                 raise ValueError(f"{name}: needs a contiguous {psi.dtype} device tensor")
-        self.params = make_params(psi.shape, psi.dtype, bc, iord, nonos, eps, tile)
+        self.params = make_params(psi.shape, psi.dtype, bc, iord, nonos, eps, tile, graph)
         self.stream = stream if stream is not None else torch.cuda.current_stream(psi.device)
         ws_bytes = _lib.mpdata_workspace_bytes(self.params)
         if ws_bytes == 0:
