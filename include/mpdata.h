@@ -196,6 +196,46 @@ int mpdata_batch_profile_step(mpdata_batch *b, int64_t *cycles_out, int32_t nseg
 int mpdata_batch_mass(mpdata_batch *b, int32_t i, double *out);
 
 int mpdata_batch_sync(mpdata_batch *b);
+
+/* -------------------------------------------------------------------- pools
+ * A pool is a batch whose membership changes between calls: the serving
+ * engine of continuous batching.  Grids join (mpdata_pool_add, validated
+ * once) and leave (mpdata_pool_remove) at any time between steps; every
+ * mpdata_pool_step advances all current members by the same number of
+ * steps with one persistent launch per step over a plan rebuilt on the host
+ * for the current members and uploaded asynchronously.  All members share
+ * dtype, bc, nonos, eps and the launch shape given at creation (iord 2).
+ * Each member brings its own second psi buffer (psi_scratch, same size as
+ * psi); after every mpdata_pool_step a member's state is in its psi. */
+typedef struct mpdata_pool mpdata_pool; /* opaque */
+
+/* Workspace bytes of a pool with at most max_grids members whose plans hold
+ * at most max_segments segments. */
+size_t mpdata_pool_workspace_bytes(int32_t max_grids, int32_t max_segments);
+
+/* shared: dtype, bc, nonos, eps, tile and flags of every member (its nx, ny,
+ * nz, iord are ignored). */
+int mpdata_pool_create(const mpdata_params *shared, int32_t max_grids, int32_t max_segments,
+                       void *workspace, size_t ws_bytes, void *stream, mpdata_pool **out);
+
+/* Adds a grid; the checks of mpdata_create run on validate_stream (the
+ * stream the arrays were written on; NULL = the pool's stream), which is
+ * synchronised.  *slot receives its id (>= 0). */
+int mpdata_pool_add(mpdata_pool *pool, int32_t nx, int32_t ny, int32_t nz, void *psi,
+                    void *psi_scratch, const void *u1, const void *u2, const void *u3,
+                    const void *h, void *validate_stream, int32_t *slot);
+
+/* Removes a member (its arrays are no longer referenced after the work
+ * already enqueued on the pool's stream). */
+int mpdata_pool_remove(mpdata_pool *pool, int32_t slot);
+
+/* nsteps >= 0 steps of every member (asynchronous on the pool's stream). */
+int mpdata_pool_step(mpdata_pool *pool, int32_t nsteps);
+
+int32_t mpdata_pool_size(const mpdata_pool *pool);             /* current members */
+int mpdata_pool_sync(mpdata_pool *pool);
+void mpdata_pool_destroy(mpdata_pool *pool);                   /* NULL-safe */
+const char *mpdata_pool_last_error(const mpdata_pool *pool);   /* NULL: last create */
 void mpdata_batch_destroy(mpdata_batch *b);                 /* NULL-safe */
 const char *mpdata_batch_last_error(const mpdata_batch *b); /* NULL: last create */
 

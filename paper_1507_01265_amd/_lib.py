@@ -92,6 +92,20 @@ _SIGNATURES = {
     "mpdata_batch_sync": ([ctypes.c_void_p], ctypes.c_int),
     "mpdata_batch_destroy": ([ctypes.c_void_p], None),
     "mpdata_batch_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
+    "mpdata_pool_workspace_bytes": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_size_t),
+    "mpdata_pool_create": ([ctypes.POINTER(mpdata_params), ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                            ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "mpdata_pool_add": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "mpdata_pool_remove": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int),
+    "mpdata_pool_step": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int),
+    "mpdata_pool_size": ([ctypes.c_void_p], ctypes.c_int32),
+    "mpdata_pool_sync": ([ctypes.c_void_p], ctypes.c_int),
+    "mpdata_pool_destroy": ([ctypes.c_void_p], None),
+    "mpdata_pool_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
 }
 
 
@@ -123,9 +137,11 @@ def hip_runtimes_mapped():
     return sorted(paths)
 
 
-def check(code: int, ctx=None, batch=False):
+def check(code: int, ctx=None, batch=False, pool=False):
     if code != MPDATA_OK:
-        fn = load().mpdata_batch_last_error if batch else load().mpdata_last_error
+        lib = load()
+        fn = (lib.mpdata_pool_last_error if pool else
+              lib.mpdata_batch_last_error if batch else lib.mpdata_last_error)
         msg = fn(ctx).decode(errors="replace")
         raise MpdataError(code, msg)
 
@@ -270,3 +286,48 @@ def mpdata_batch_destroy(b):
 
 def mpdata_batch_last_error(b=None) -> str:
     return load().mpdata_batch_last_error(b).decode(errors="replace")
+
+
+# -------------------------------------------------------------------- pools
+
+def mpdata_pool_workspace_bytes(max_grids: int, max_segments: int) -> int:
+    return int(load().mpdata_pool_workspace_bytes(max_grids, max_segments))
+
+
+def mpdata_pool_create(shared: mpdata_params, max_grids: int, max_segments: int, workspace,
+                       ws_bytes: int, stream):
+    out = ctypes.c_void_p()
+    check(load().mpdata_pool_create(ctypes.byref(shared), max_grids, max_segments, workspace,
+                                    ws_bytes, stream, ctypes.byref(out)), None, pool=True)
+    return out.value
+
+
+def mpdata_pool_add(pool, nx, ny, nz, psi, psi_scratch, u1, u2, u3, h, validate_stream) -> int:
+    slot = ctypes.c_int32()
+    check(load().mpdata_pool_add(pool, nx, ny, nz, psi, psi_scratch, u1, u2, u3, h,
+                                 validate_stream, ctypes.byref(slot)), pool, pool=True)
+    return slot.value
+
+
+def mpdata_pool_remove(pool, slot: int):
+    check(load().mpdata_pool_remove(pool, slot), pool, pool=True)
+
+
+def mpdata_pool_step(pool, nsteps: int):
+    check(load().mpdata_pool_step(pool, nsteps), pool, pool=True)
+
+
+def mpdata_pool_size(pool) -> int:
+    return int(load().mpdata_pool_size(pool))
+
+
+def mpdata_pool_sync(pool):
+    check(load().mpdata_pool_sync(pool), pool, pool=True)
+
+
+def mpdata_pool_destroy(pool):
+    load().mpdata_pool_destroy(pool)
+
+
+def mpdata_pool_last_error(pool=None) -> str:
+    return load().mpdata_pool_last_error(pool).decode(errors="replace")

@@ -26,6 +26,7 @@ constexpr size_t kAlign = 256;
 constexpr int kMassParts = 1024;  // blocks of the mass reduction (fixed: deterministic)
 constexpr int kGraphSteps = 8;    // steps per replayed graph (even: psi ends where it began)
 constexpr int kXcds = 8;          // XCDs of an MI355X; workgroup w runs on XCD w % 8
+constexpr int kMinShare = 24;     // fewest planes a workgroup's share of a plan marches
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -101,8 +102,14 @@ void default_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
                 work += grids[g].nz;
             }
     }
+    // Each share should march at least kMinShare planes: a segment pays
+    // PRIMING extra iterations before its first output, so tiny shares would
+    // be mostly pipeline fill.  With little work only the first shares (one
+    // per XCD first) are used.
+    const int nwg_all = nwg;
+    nwg = (int)std::max(1LL, std::min<long long>(nwg, work / kMinShare));
     // logical share l covers work units [l*work/nwg, (l+1)*work/nwg)
-    std::vector<std::vector<mpd::Segment>> share(nwg);
+    std::vector<std::vector<mpd::Segment>> share(nwg_all);
     size_t ti = 0;
     long long tile_start = 0;  // work offset of tiles[ti]
     for (int l = 0; l < nwg; ++l) {
@@ -126,15 +133,23 @@ void default_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
             }
         }
     }
-    const int per_xcd = nwg % kXcds == 0 ? nwg / kXcds : 0;
+    // physical workgroup w runs on XCD w % 8: consecutive logical shares go
+    // to the same XCD; when fewer shares than workgroups are used they are
+    // spread over the XCDs first
+    const int per_xcd = nwg_all % kXcds == 0 ? nwg_all / kXcds : 0;
     segs.clear();
-    wg_begin.assign(nwg + 1, 0);
-    for (int w = 0; w < nwg; ++w) {
-        const int l = per_xcd ? (w % kXcds) * per_xcd + w / kXcds : w;
+    wg_begin.assign(nwg_all + 1, 0);
+    for (int w = 0; w < nwg_all; ++w) {
+        int l = w;
+        if (per_xcd) {
+            const int x = w % kXcds, i = w / kXcds;          // XCD, index within it
+            const int used_per_xcd = (nwg + kXcds - 1) / kXcds;
+            l = i < used_per_xcd ? x * used_per_xcd + i : nwg;  // beyond nwg: idle
+        }
         wg_begin[w] = (int)segs.size();
-        segs.insert(segs.end(), share[l].begin(), share[l].end());
+        if (l < nwg) segs.insert(segs.end(), share[l].begin(), share[l].end());
     }
-    wg_begin[nwg] = (int)segs.size();
+    wg_begin[nwg_all] = (int)segs.size();
 }
 
 // A plan must cover every output tile of every grid over all its planes
@@ -521,6 +536,110 @@ static void default_bounds(int n, const mpdata_params *params, int tile, int *ns
     default_plan_bounds(v, tile, *nwg, nseg);
 }
 
+
+// -------------------------------------------------------------------- pools
+
+struct mpdata_pool {
+    Engine e;                 // dtype, tile, open, nonos, eps, stream, graph
+    int max_grids, max_segs, nwg_all;
+    struct Slot {
+        bool used;
+        mpdata_params p;
+        mpd::GridDesc<double> g;
+    };
+    std::vector<Slot> slots;
+    bool dirty;               // membership changed since the last upload
+    // pinned host staging of the plan, double-buffered against in-flight copies
+    struct Stage {
+        char *host;
+        hipEvent_t done;
+        bool pending;
+    } stage[2];
+    int cur_stage;
+    size_t stage_bytes;
+};
+
+static int pool_fail(mpdata_pool *p, int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(p ? p->e.err : g_create_err, 256, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static Layout pool_layout(int max_grids, int max_segs, int max_wg)
+{
+    // no psi copies in the workspace: members bring their own second buffer
+    Layout l;
+    size_t off = 0;
+    l.psi2 = 0;
+    l.grids = off;
+    off += align_up((size_t)max_grids * sizeof(mpd::GridDesc<double>));
+    l.segs = off;
+    off += align_up((size_t)max_segs * sizeof(mpd::Segment));
+    l.wg = off;
+    off += align_up(((size_t)max_wg + 1) * sizeof(int));
+    l.ticks = off;
+    l.partials = off;
+    off += align_up((size_t)kMassParts * 2 * sizeof(double));
+    l.result = off;
+    off += align_up(2 * sizeof(double));
+    l.flags = off;
+    off += align_up(4 * sizeof(unsigned int));
+    l.total = off;
+    return l;
+}
+
+// Uploads descriptors and the default plan of the current members.
+static int pool_upload(mpdata_pool *p)
+{
+    Engine &e = p->e;
+    std::vector<mpdata_params> ps;
+    std::vector<mpd::GridDesc<double>> gs;
+    for (const auto &s : p->slots)
+        if (s.used) {
+            ps.push_back(s.p);
+            gs.push_back(s.g);
+        }
+    e.ngrids = (int)gs.size();
+    if (e.ngrids == 0) return MPDATA_OK;
+    std::vector<mpd::Segment> segs;
+    std::vector<int> wg;
+    default_plan(ps, e.tile, p->nwg_all, segs, wg);
+    if ((int)segs.size() > p->max_segs)
+        return pool_fail(p, MPDATA_ENOMEM, "plan needs %zu segments > max_segments %d", segs.size(),
+                         p->max_segs);
+    e.nwg = (int)wg.size() - 1;
+    e.nseg = (int)segs.size();
+    mpdata_pool::Stage &st = p->stage[p->cur_stage];
+    p->cur_stage ^= 1;
+    if (st.pending) {
+        hipError_t r = hipEventSynchronize(st.done);
+        if (r != hipSuccess) return pool_fail(p, MPDATA_EDEVICE, "staging wait: %s", hipGetErrorString(r));
+    }
+    const size_t bg = gs.size() * sizeof(mpd::GridDesc<double>);
+    const size_t bs = segs.size() * sizeof(mpd::Segment);
+    const size_t bw = wg.size() * sizeof(int);
+    memcpy(st.host, gs.data(), bg);
+    memcpy(st.host + align_up(bg), segs.data(), bs);
+    memcpy(st.host + align_up(bg) + align_up(bs), wg.data(), bw);
+    hipError_t r = hipMemcpyAsync(e.ws + e.lay.grids, st.host, bg, hipMemcpyHostToDevice, e.stream);
+    if (r == hipSuccess)
+        r = hipMemcpyAsync(e.ws + e.lay.segs, st.host + align_up(bg), bs, hipMemcpyHostToDevice, e.stream);
+    if (r == hipSuccess)
+        r = hipMemcpyAsync(e.ws + e.lay.wg, st.host + align_up(bg) + align_up(bs), bw,
+                           hipMemcpyHostToDevice, e.stream);
+    if (r == hipSuccess) r = hipEventRecord(st.done, e.stream);
+    if (r != hipSuccess) return pool_fail(p, MPDATA_EDEVICE, "plan upload: %s", hipGetErrorString(r));
+    st.pending = true;
+    p->dirty = false;
+    // a replayed graph stays valid: it holds only the workspace addresses of
+    // the plan (whose contents were just replaced, in stream order) and the
+    // workgroup count, which the default plan keeps at nwg_all
+    return MPDATA_OK;
+}
+
 extern "C" {
 
 int mpdata_abi_version(void) { return MPDATA_ABI_VERSION; }
@@ -752,5 +871,197 @@ void mpdata_batch_destroy(mpdata_batch *b)
 }
 
 const char *mpdata_batch_last_error(const mpdata_batch *b) { return b ? b->e.err : g_create_err; }
+
+
+// -------------------------------------------------------------------- pools
+
+size_t mpdata_pool_workspace_bytes(int32_t max_grids, int32_t max_segments)
+{
+    if (max_grids < 1 || max_segments < 1) return 0;
+    return pool_layout(max_grids, max_segments, 256 * 8).total;
+}
+
+int mpdata_pool_create(const mpdata_params *shared, int32_t max_grids, int32_t max_segments,
+                       void *workspace, size_t ws_bytes, void *stream, mpdata_pool **out)
+{
+    g_create_err[0] = 0;
+    if (!out) return pool_fail(nullptr, MPDATA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!shared) return pool_fail(nullptr, MPDATA_EINVAL, "shared params is NULL");
+    mpdata_params sp = *shared;
+    sp.nx = sp.ny = sp.nz = 1;
+    sp.iord = 2;
+    if (const char *m = check_params(&sp)) return pool_fail(nullptr, MPDATA_EINVAL, "%s", m);
+    if (max_grids < 1 || max_segments < 1)
+        return pool_fail(nullptr, MPDATA_EINVAL, "max_grids and max_segments must be >= 1");
+    if (!workspace || ((uintptr_t)workspace & (kAlign - 1)) != 0)
+        return pool_fail(nullptr, MPDATA_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    const size_t need = mpdata_pool_workspace_bytes(max_grids, max_segments);
+    if (ws_bytes < need)
+        return pool_fail(nullptr, MPDATA_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    mpdata_pool *p = new (std::nothrow) mpdata_pool;
+    if (!p) return pool_fail(nullptr, MPDATA_ENOMEM, "host allocation failed");
+    Engine &e = p->e;
+    e.dtype = sp.dtype;
+    e.tile = tile_of(&sp);
+    e.iord = 2;
+    e.open = sp.bc == MPDATA_BC_OPEN;
+    e.nonos = sp.nonos != 0;
+    e.eps = sp.eps;
+    e.use_graph = !(sp.flags & MPDATA_FLAG_NO_GRAPH);
+    e.stream = (hipStream_t)stream;
+    e.ws = (char *)workspace;
+    e.ngrids = 0;
+    e.nwg = 0;
+    e.nseg = 0;
+    e.err[0] = 0;
+    e.params.assign(1, sp);
+    const int per = wg_per_cu(e.dtype, e.tile, e.open, e.nonos);
+    const int cus = device_cus();
+    if (per < 1 || cus < 1) {
+        delete p;
+        return pool_fail(nullptr, MPDATA_EDEVICE, "occupancy query failed");
+    }
+    p->nwg_all = std::min(per * cus, 256 * 8);
+    p->max_grids = max_grids;
+    p->max_segs = max_segments;
+    e.lay = pool_layout(max_grids, max_segments, 256 * 8);
+    p->slots.assign(max_grids, mpdata_pool::Slot{false, sp, {}});
+    p->dirty = false;
+    p->cur_stage = 0;
+    p->stage_bytes = align_up((size_t)max_grids * sizeof(mpd::GridDesc<double>)) +
+                     align_up((size_t)max_segments * sizeof(mpd::Segment)) +
+                     align_up(((size_t)p->nwg_all + 1) * sizeof(int));
+    for (auto &st : p->stage) {
+        st.host = nullptr;
+        st.pending = false;
+        st.done = nullptr;
+    }
+    for (auto &st : p->stage) {
+        hipError_t r = hipHostMalloc((void **)&st.host, p->stage_bytes, hipHostMallocDefault);
+        if (r == hipSuccess) r = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+        if (r != hipSuccess) {
+            mpdata_pool_destroy(p);
+            return pool_fail(nullptr, MPDATA_EDEVICE, "pinned staging: %s", hipGetErrorString(r));
+        }
+    }
+    *out = p;
+    return MPDATA_OK;
+}
+
+int mpdata_pool_add(mpdata_pool *p, int32_t nx, int32_t ny, int32_t nz, void *psi,
+                    void *psi_scratch, const void *u1, const void *u2, const void *u3,
+                    const void *h, void *validate_stream, int32_t *slot)
+{
+    if (!p) return MPDATA_EINVAL;
+    if (!slot) return pool_fail(p, MPDATA_EINVAL, "slot is NULL");
+    Engine &e = p->e;
+    mpdata_params gp = e.params[0];
+    gp.nx = nx;
+    gp.ny = ny;
+    gp.nz = nz;
+    if (const char *m = check_params(&gp)) return pool_fail(p, MPDATA_EINVAL, "%s", m);
+    if (!psi || !psi_scratch || !u1 || !u2 || !u3 || !h)
+        return pool_fail(p, MPDATA_EINVAL, "NULL array pointer");
+    if (misaligned(psi) || misaligned(psi_scratch) || misaligned(u1) || misaligned(u2) ||
+        misaligned(u3) || misaligned(h))
+        return pool_fail(p, MPDATA_EINVAL, "arrays must be 16-byte aligned");
+    int free_slot = -1;
+    for (int i = 0; i < p->max_grids; ++i)
+        if (!p->slots[i].used) {
+            free_slot = i;
+            break;
+        }
+    if (free_slot < 0) return pool_fail(p, MPDATA_ENOMEM, "pool full (%d members)", p->max_grids);
+    // the checks of mpdata_create, on the caller's stream
+    hipStream_t vs = validate_stream ? (hipStream_t)validate_stream : e.stream;
+    unsigned int *flags = (unsigned int *)(e.ws + e.lay.flags);
+    hipError_t r = hipMemsetAsync(flags, 0, 4 * sizeof(unsigned int), vs);
+    const int periodic = gp.bc == MPDATA_BC_PERIODIC;
+    if (r == hipSuccess)
+        r = e.dtype == MPDATA_FP64
+                ? mpd::launch_validate<double>((const double *)h, (const double *)u1,
+                                               (const double *)u2, (const double *)u3, nx, ny, nz,
+                                               periodic, flags, vs)
+                : mpd::launch_validate<float>((const float *)h, (const float *)u1,
+                                              (const float *)u2, (const float *)u3, nx, ny, nz,
+                                              periodic, flags, vs);
+    unsigned int hf[2] = {0, 0};
+    if (r == hipSuccess) r = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, vs);
+    if (r == hipSuccess) r = hipStreamSynchronize(vs);
+    if (r != hipSuccess) return pool_fail(p, MPDATA_EDEVICE, "validate: %s", hipGetErrorString(r));
+    if (hf[0]) return pool_fail(p, MPDATA_EINVAL, "h must be finite and > 0 (%u bad cells)", hf[0]);
+    if (hf[1])
+        return pool_fail(p, MPDATA_EINVAL,
+                         "periodic boundaries need face n == face 0 on every axis (%u differ)", hf[1]);
+    mpdata_pool::Slot &s = p->slots[free_slot];
+    s.used = true;
+    s.p = gp;
+    s.g.u1 = (const double *)u1;
+    s.g.u2 = (const double *)u2;
+    s.g.u3 = (const double *)u3;
+    s.g.h = (const double *)h;
+    s.g.psi[0] = (double *)psi;
+    s.g.psi[1] = (double *)psi_scratch;
+    s.g.nx = nx;
+    s.g.ny = ny;
+    s.g.nz = nz;
+    s.g.pad = 0;
+    p->dirty = true;
+    *slot = free_slot;
+    return MPDATA_OK;
+}
+
+int mpdata_pool_remove(mpdata_pool *p, int32_t slot)
+{
+    if (!p) return MPDATA_EINVAL;
+    if (slot < 0 || slot >= p->max_grids || !p->slots[slot].used)
+        return pool_fail(p, MPDATA_EINVAL, "no member in slot %d", slot);
+    p->slots[slot].used = false;
+    p->dirty = true;
+    return MPDATA_OK;
+}
+
+int mpdata_pool_step(mpdata_pool *p, int32_t nsteps)
+{
+    if (!p) return MPDATA_EINVAL;
+    if (nsteps < 0) return pool_fail(p, MPDATA_EINVAL, "nsteps must be >= 0");
+    if (p->dirty) {
+        const int rc = pool_upload(p);
+        if (rc != MPDATA_OK) return rc;
+    }
+    if (p->e.ngrids == 0 || nsteps == 0) return MPDATA_OK;
+    return engine_step(p->e, nsteps);
+}
+
+int32_t mpdata_pool_size(const mpdata_pool *p)
+{
+    if (!p) return -1;
+    int n = 0;
+    for (const auto &s : p->slots) n += s.used;
+    return n;
+}
+
+int mpdata_pool_sync(mpdata_pool *p)
+{
+    if (!p) return MPDATA_EINVAL;
+    hipError_t r = hipStreamSynchronize(p->e.stream);
+    return r == hipSuccess ? MPDATA_OK
+                           : pool_fail(p, MPDATA_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(r));
+}
+
+void mpdata_pool_destroy(mpdata_pool *p)
+{
+    if (!p) return;
+    (void)hipStreamSynchronize(p->e.stream);
+    engine_release(p->e);
+    for (auto &st : p->stage) {
+        if (st.done) hipEventDestroy(st.done);
+        if (st.host) hipHostFree(st.host);
+    }
+    delete p;
+}
+
+const char *mpdata_pool_last_error(const mpdata_pool *p) { return p ? p->e.err : g_create_err; }
 
 }  // extern "C"

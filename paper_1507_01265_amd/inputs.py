@@ -219,6 +219,35 @@ def rotation_request(rng: np.random.Generator, nx: int, ny: int, nz: int,
     return Fields(psi, u1, u2, u3, np.ones(shape), BC_PERIODIC)
 
 
+def rotation_request_device(req: "Request", device="cuda"):
+    """The fields of ``req`` built directly in device memory with torch (same
+    recipe as :func:`rotation_request`; values may differ from the numpy
+    build in the last bits of exp).  Returns (psi, u1, u2, u3, h)."""
+    import torch
+    rng = _rng(req.field_seed)
+    nz, ny, nx = req.shape
+    centre = (nx * rng.uniform(0.3, 0.7), ny * rng.uniform(0.3, 0.7), nz / 2)
+    sigma = max(2.0, min(req.shape) / 8.0)
+    omega = 0.5 / (max(nx, ny) / 2 - 0.5)
+    f64 = dict(dtype=torch.float64, device=device)
+    yc = torch.arange(ny, **f64) + 0.5 - ny / 2
+    xc = torch.arange(nx, **f64) + 0.5 - nx / 2
+    u1 = (-req.sense * omega * yc)[None, :, None].expand(nz, ny, nx + 1)
+    u2 = (req.sense * omega * xc)[None, None, :].expand(nz, ny + 1, nx)
+    u3 = torch.zeros((nz + 1, ny, nx), **f64)
+    h = torch.ones((nz, ny, nx), **f64)
+
+    def d(n, c):
+        v = torch.arange(n, **f64) + 0.5 - c
+        return v - n * torch.round(v / n)
+
+    dz, dy, dx = d(nz, centre[2]), d(ny, centre[1]), d(nx, centre[0])
+    r2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
+    psi = 1.0 + torch.exp(-r2 / (2.0 * sigma * sigma))
+    dt = torch.float32 if req.fp32 else torch.float64
+    return tuple(t.to(dt).contiguous() for t in (psi, u1, u2, u3, h))
+
+
 @dataclasses.dataclass
 class Request:
     rid: int
