@@ -35,6 +35,14 @@ WORKLOADS = {
                             "streamfunction 1024x512x64 open FP32 + FP64 limiter, limiter on, iord 2"),
     "streamfunction-fp64": ("streamfunction", "f64",
                             "streamfunction 1024x512x64 open FP64, limiter on, iord 2"),
+    "batched-fp32": ("batched", "f32",
+                     "96 uneven periodic grids (nx, ny log-uniform in [32, 384], nz in [16, 64]), "
+                     "FP32 + FP64 limiter, constant Courant per grid, one persistent launch per "
+                     "step"),
+    "served": ("served", "mixed",
+               "Poisson arrivals 200/s for 60 s, dims log-uniform [32,256]^2 x [16,64], steps "
+               "uniform [10,200], 70% FP32 / 30% FP64, solid-body rotation, 200 GB HBM budget, "
+               "continuous batching"),
 }
 
 
@@ -46,6 +54,33 @@ def algorithmic_bytes(shape, word):
     n = nx * ny * nz
     faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
     return word * (3 * n + faces)
+
+
+PROFILES = {"rotation-fp64": "step_kernel_rotation_512x256x64_fp64.md",
+            "rotation-fp32": "step_kernel_rotation_512x256x64_fp32.md",
+            "streamfunction-fp32": "step_kernel_streamfunction_1024x512x64_fp32.md"}
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    summary of this workload (FETCH_SIZE and WRITE_SIZE runs, each scaled by
+    the same counter on a 512 MiB copy), or None when there is none or the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    name = PROFILES.get(workload)
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_1507_01265_amd", "csrc", "mpdata_step.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def make_fields(kind):
@@ -96,6 +131,116 @@ def cpu_baseline(fields, budget_s=12.0, max_steps=40):
     return steps, el
 
 
+def time_region(fn, stream):
+    import torch
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def bench_batched(args):
+    """96 uneven grids, FP32, K steps: one persistent launch per step over
+    all grids (library plan and tuned plan) against the same grids advanced
+    one after another through the single-grid path."""
+    import numpy as np
+    import torch
+    from paper_1507_01265_amd import autotune, inputs
+    from paper_1507_01265_amd.batch import Batch
+    from paper_1507_01265_amd.solver import Solver
+
+    print("# generating 96 grids", file=sys.stderr, flush=True)
+    fs = [f.astype(np.float32) for f in inputs.batched_grids(96)]
+    grids = [tuple(torch.from_numpy(a).cuda() for a in (f.psi, f.u1, f.u2, f.u3, f.h)) for f in fs]
+    cells = sum(g[0].numel() for g in grids)
+    saved = [g[0].clone() for g in grids]
+    K, W = args.steps, args.warmup
+
+    def restore():
+        for g, s0 in zip(grids, saved):
+            g[0].copy_(s0)
+
+    out = {}
+    print("# batched, library plan", file=sys.stderr, flush=True)
+    b = Batch(grids)
+    b.step(W)
+    ms_default = time_region(lambda: b.step(K), b.stream)
+    b.close()
+    restore()
+    print("# tuning", file=sys.stderr, flush=True)
+    tuned = autotune.tune(grids, steps=4, profiles=3)
+    b = Batch(grids, plan=tuned.plan)
+    b.step(W)
+    restore()
+    ms_tuned = time_region(lambda: b.step(K), b.stream)
+    torch.cuda.synchronize()
+    result_tuned = [g[0].clone() for g in grids]
+    b.close()
+    restore()
+    print("# single-grid path, one grid after another", file=sys.stderr, flush=True)
+    solvers = [Solver(*g, tile=5) for g in grids]
+    for s_ in solvers:
+        s_.step(W)
+    restore()
+    stream = solvers[0].stream
+
+    def seq():
+        for s_ in solvers:
+            s_.step(K)
+    ms_single = time_region(seq, stream)
+    same = all(torch.equal(g[0], r) for g, r in zip(grids, result_tuned))
+    for s_ in solvers:
+        s_.close()
+    best = min(ms_default, ms_tuned)
+    out.update(ms=best, cells=cells, steps=K,
+               extra={"ms_library_plan": ms_default, "ms_tuned_plan": ms_tuned,
+                      "ms_single_grid_sequence": ms_single,
+                      "speedup_vs_single_grid": ms_single / best,
+                      "tuned_tile": tuned.tile, "tuner_log": tuned.log,
+                      "bitwise_equal_to_single_grid": bool(same),
+                      "grids": len(grids)})
+    return out
+
+
+def bench_served(args):
+    """Poisson arrivals replayed in real time against the continuous-batching
+    server; the plain single-grid path serving the first arrivals one after
+    another gives the comparison."""
+    import numpy as np
+    import torch
+    from paper_1507_01265_amd import inputs, serve
+    from paper_1507_01265_amd.solver import Solver
+
+    reqs = inputs.served_requests(rate=args.rate, duration=args.duration, seed=5000)
+    print(f"# serving {len(reqs)} requests over {args.duration} s", file=sys.stderr, flush=True)
+    warm = serve.Server(200e9)
+    warm.run(inputs.served_requests(rate=50, duration=0.2, seed=1), realtime=False)
+    warm.close()
+    srv = serve.Server(args.budget)
+    done = srv.run(reqs, realtime=True, log_every=10.0)
+    summ = serve.summarize(done, srv.elapsed)
+    stats = dict(srv.stats)
+    srv.close()
+    # plain single-grid path: the first requests, one at a time, back to back
+    sample = reqs[:200]
+    t0 = time.perf_counter()
+    cu = 0
+    for r in sample:
+        f = inputs.rotation_request_device(r)
+        s_ = Solver(*f)
+        s_.step(r.steps)
+        out = s_.psi.cpu()
+        s_.close()
+        cu += r.cells * r.steps
+    single_rate = cu / (time.perf_counter() - t0)
+    return {"summary": summ, "stats": stats, "single_grid_cell_updates_per_s": single_rate,
+            "single_grid_sample": len(sample)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +250,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="launch shape id (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="served: seconds of arrivals")
+    ap.add_argument("--budget", type=float, default=200e9, help="served: HBM budget in bytes")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-MiB device buffer once (a copy kernel of "
                          "known size for scaling HBM counters)")
@@ -122,6 +270,30 @@ def main():
         sys.exit(1)
 
     kind, dtag, desc = WORKLOADS[args.workload]
+    if kind == "batched":
+        r = bench_batched(args)
+        line = {"metric": "MPDATA cell-updates/s per step", "value": r["cells"] * r["steps"] / (r["ms"] / 1e3),
+                "unit": "cell-updates/s", "n_gpus": 1, "steps": r["steps"], "warmup": args.warmup,
+                "ms_per_step": r["ms"] / r["steps"], "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded generator, resident in HBM)",
+                "config": {"workload": desc, "cells": r["cells"]}}
+        line.update(r["extra"])
+        print(json.dumps(line), flush=True)
+        return
+    if kind == "served":
+        r = bench_served(args)
+        sm = r["summary"]
+        line = {"metric": "MPDATA cell-updates/s (served), p50/p99 latency", "value": sm["cell_updates_per_s"],
+                "unit": "cell-updates/s", "n_gpus": 1, "steps": None, "warmup": None,
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "mixed f32/f64",
+                "data": "synthetic (seeded Poisson arrivals, fields built on the device)",
+                "config": {"workload": desc, "rate": args.rate, "duration_s": args.duration,
+                           "budget_bytes": args.budget},
+                "p50_ms": sm["p50_ms"], "p99_ms": sm["p99_ms"], "served": sm, "server": r["stats"],
+                "single_grid_cell_updates_per_s": r["single_grid_cell_updates_per_s"],
+                "single_grid_sample_requests": r["single_grid_sample"]}
+        print(json.dumps(line), flush=True)
+        return
     print(f"# generating {args.workload}", file=sys.stderr, flush=True)
     fields = make_fields(kind)
     nz, ny, nx = fields.shape
@@ -152,7 +324,7 @@ def main():
                    "bc": "periodic" if fields.bc == 0 else "open", "iord": 2, "nonos": True,
                    "tile": args.tile},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "algorithmic_bytes_per_launch": abytes},
         "mass_drift": (g["mass1"] - g["mass0"]) / g["mass0"],
         "psi_min": g["psi_min"],

@@ -153,6 +153,20 @@ __device__ __forceinline__ T limited(T v, double bup_a, double bdn_a, double bup
     return cp * pos(v) + cn * neg(v);
 }
 
+// Pointers read from a grid descriptor are generic; marking them as global
+// memory makes the compiler emit global (not flat) loads, which do not share
+// the LDS wait counter.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(T *p) { return (gptr<T>)p; }
+
+// Element at a 32-bit byte offset from a workgroup-uniform base: the address
+// is base + zext(offset), which maps onto the scalar-base + vector-offset
+// form of the global loads (no 64-bit address arithmetic per load).
+template <typename T> __device__ __forceinline__ T ld(gptr<const T> base, unsigned byte_off)
+{
+    return *(gptr<const T>)((__attribute__((address_space(1))) const char *)base + byte_off);
+}
+
 // Registers of one plane of a column: the Courant numbers of its x- and
 // y-faces and h (needed one iteration ahead) ...
 template <typename T> struct PlaneA {
@@ -197,8 +211,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const T eps = T(eps_d);
     const L eps_l = eps_d;
-    const T *__restrict__ psi_in = g.psi[flip];
-    T *__restrict__ psi_out = g.psi[1 - flip];
+    const gptr<const T> psi_in = as_global<const T>(g.psi[flip]);
+    const gptr<T> psi_out = as_global<T>(g.psi[1 - flip]);
+    const gptr<const T> gh = as_global<const T>(g.h), gu1 = as_global<const T>(g.u1);
+    const gptr<const T> gu2 = as_global<const T>(g.u2), gu3 = as_global<const T>(g.u3);
 
     const int tid = threadIdx.x;
     const int lx = tid % RX, ly = tid / RX;
@@ -220,6 +236,12 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     const bool has_ry = (ly == 0) || (ly == RY - 1);
     const unsigned o_rx = cy * nx + cell_of<OPEN>(lx == 0 ? gx - 1 : gx + 1, nx);
     const unsigned o_ry = cell_of<OPEN>(ly == 0 ? gy - 1 : gy + 1, ny) * nx + cx;
+    // byte offsets within a plane (a plane of any array stays below 4 GiB:
+    // the host limits every array to 2^31 elements)
+    const unsigned b_c = o_c * (unsigned)sizeof(T);
+    const unsigned b_u1lo = o_u1lo * (unsigned)sizeof(T), b_u1hi = o_u1hi * (unsigned)sizeof(T);
+    const unsigned b_u2lo = o_u2lo * (unsigned)sizeof(T), b_u2hi = o_u2hi * (unsigned)sizeof(T);
+    const unsigned b_rx = o_rx * (unsigned)sizeof(T), b_ry = o_ry * (unsigned)sizeof(T);
     const int p_rx = q + (lx == 0 ? XM : XP);
     const int p_ry = q + (ly == 0 ? YM : YP);
 
@@ -244,22 +266,22 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         return k + 1 == nz ? 0 : k + 1;
     };
     auto load_a = [&](int k, PlaneA<T> &r) {
-        const T *__restrict__ hp = g.h + (size_t)k * pc_cells;
-        const T *__restrict__ u1p = g.u1 + (size_t)k * pc_u1;
-        const T *__restrict__ u2p = g.u2 + (size_t)k * pc_u2;
-        r.h = hp[o_c];
-        r.u1lo = u1p[o_u1lo];
-        r.u1hi = u1p[o_u1hi];
-        r.u2lo = u2p[o_u2lo];
-        r.u2hi = u2p[o_u2hi];
+        const gptr<const T> hp = gh + (size_t)k * pc_cells;
+        const gptr<const T> u1p = gu1 + (size_t)k * pc_u1;
+        const gptr<const T> u2p = gu2 + (size_t)k * pc_u2;
+        r.h = ld(hp, b_c);
+        r.u1lo = ld(u1p, b_u1lo);
+        r.u1hi = ld(u1p, b_u1hi);
+        r.u2lo = ld(u2p, b_u2lo);
+        r.u2hi = ld(u2p, b_u2hi);
     };
     auto load_b = [&](int k, int kf, PlaneB<T> &r) {
-        const T *__restrict__ pp = psi_in + (size_t)k * pc_cells;
-        const T *__restrict__ u3p = g.u3 + (size_t)kf * pc_cells;
-        r.pn = pp[o_c];
-        r.u3lo = u3p[o_c];
-        r.ringx = has_rx ? pp[o_rx] : T(0);
-        r.ringy = has_ry ? pp[o_ry] : T(0);
+        const gptr<const T> pp = psi_in + (size_t)k * pc_cells;
+        const gptr<const T> u3p = gu3 + (size_t)kf * pc_cells;
+        r.pn = ld(pp, b_c);
+        r.u3lo = ld(u3p, b_c);
+        r.ringx = has_rx ? ld(pp, b_rx) : T(0);
+        r.ringy = has_ry ? ld(pp, b_ry) : T(0);
     };
     auto store_ring = [&](const PlaneB<T> &r) {
         sP[q] = r.pn;
@@ -278,7 +300,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     load_a(plane_of(t0), curA);
     load_b(plane_of(t0), zface_of(t0), cur);
     load_b(ka, zface_of(t0 + 1), nx1);
-    const T pn_prev = psi_in[(size_t)plane_of(t0 - 1) * pc_cells + o_c];
+    const T pn_prev = ld(psi_in + (size_t)plane_of(t0 - 1) * pc_cells, b_c);
     store_ring(cur);
 
     // z-history of the column
@@ -406,7 +428,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
             // ---- S7 at plane r = t-2
             const T fc1hi = sFC1[q + XP], fc2hi = sFC2[q + YP];
             const T res = p1_m2 - (((fc1hi - sFC1[q]) + (fc2hi - sFC2[q])) + (fc3_m1 - fc3_m2)) * rh_m2;
-            if (is_out && t >= z0 + 2 && t <= tend) (psi_out + (size_t)(t - 2) * pc_cells)[o_c] = res;
+            if (is_out && t >= z0 + 2 && t <= tend)
+                *(gptr<T>)((__attribute__((address_space(1))) char *)(psi_out + (size_t)(t - 2) * pc_cells) + b_c) = res;
         }
 
         // ---- hand the planes to the next iteration
