@@ -27,6 +27,7 @@ constexpr int kMassParts = 1024;  // blocks of the mass reduction (fixed: determ
 constexpr int kGraphSteps = 8;    // steps per replayed graph (even: psi ends where it began)
 constexpr int kXcds = 8;          // XCDs of an MI355X; workgroup w runs on XCD w % 8
 constexpr int kMinShare = 24;     // fewest planes a workgroup's share of a plan marches
+constexpr int kPipelineFill = 4;  // march iterations before a segment's first output plane
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -45,11 +46,15 @@ const mpd::TileShape &shape_of(int tile)
     return mpd::tile_shapes(&count)[tile - 1];
 }
 
-// Default launch shape per precision: the largest region whose register
-// footprint fits the workgroup without spilling.
-int default_tile(int dtype) { return dtype == MPDATA_FP32 ? 5 : 4; }
+// Default launch shape (measured on MI355X with the default plan): 32x24
+// regions, except FP32 with open boundaries, whose boundary redirects cost
+// enough registers that the 32x32 region runs faster.
+int default_tile(int dtype, int bc)
+{
+    return (dtype == MPDATA_FP32 && bc == MPDATA_BC_OPEN) ? 2 : 5;
+}
 
-int tile_of(const mpdata_params *p) { return p->tile ? p->tile : default_tile(p->dtype); }
+int tile_of(const mpdata_params *p) { return p->tile ? p->tile : default_tile(p->dtype, p->bc); }
 
 const char *check_params(const mpdata_params *p)
 {
@@ -81,13 +86,52 @@ bool misaligned(const void *ptr) { return ((uintptr_t)ptr & 15u) != 0; }
 int tiles_x(const mpdata_params &p, int tile) { return (p.nx + shape_of(tile).rx - 5) / (shape_of(tile).rx - 4); }
 int tiles_y(const mpdata_params &p, int tile) { return (p.ny + shape_of(tile).ry - 5) / (shape_of(tile).ry - 4); }
 
-// Default plan: the work of all grids, counted in (tile, plane) units and
-// listed tile by tile (grid, then tile row, then tile), is cut into nwg
-// contiguous, equal shares.  Consecutive shares go to workgroups of the same
-// XCD (workgroup w runs on XCD w % 8), so neighbouring tiles -- which re-read
-// each other's halo -- share an L2.
-void default_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
-                  std::vector<mpd::Segment> &segs, std::vector<int> &wg_begin)
+// Whole-tile plan: tile i (listed grid by grid, row by row) marches all its
+// planes on workgroup i mod nwg.  Every workgroup starts its k-th tile at the
+// same time and plane as its neighbours, so the halo lines that adjacent
+// tiles share are fetched once into L2 while both use them (measured: about
+// 15 % faster per march iteration than unaligned marches).
+void whole_tile_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
+                     std::vector<mpd::Segment> &segs, std::vector<int> &wg_begin)
+{
+    std::vector<std::vector<mpd::Segment>> per(nwg);
+    int i = 0;
+    for (int g = 0; g < (int)grids.size(); ++g) {
+        const int ntx = tiles_x(grids[g], tile), nty = tiles_y(grids[g], tile);
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx, ++i)
+                per[i % nwg].push_back(mpd::Segment{g, tx, ty, 0, grids[g].nz, 0, 0, 0});
+    }
+    segs.clear();
+    wg_begin.assign(nwg + 1, 0);
+    for (int w = 0; w < nwg; ++w) {
+        wg_begin[w] = (int)segs.size();
+        segs.insert(segs.end(), per[w].begin(), per[w].end());
+    }
+    wg_begin[nwg] = (int)segs.size();
+}
+
+// Longest march (in iterations) of a plan: planes of each segment plus the
+// pipeline fill the march pays before its first output plane.
+long long plan_makespan(const std::vector<mpd::Segment> &segs, const std::vector<int> &wg_begin)
+{
+    long long worst = 0;
+    for (size_t w = 0; w + 1 < wg_begin.size(); ++w) {
+        long long it = 0;
+        for (int s = wg_begin[w]; s < wg_begin[w + 1]; ++s)
+            it += segs[s].z1 - segs[s].z0 + kPipelineFill;
+        worst = std::max(worst, it);
+    }
+    return worst;
+}
+
+// Contiguous-share plan: the work of all grids, counted in (tile, plane)
+// units and listed tile by tile (grid, then tile row, then tile), is cut into
+// nwg contiguous, equal shares.  Consecutive shares go to workgroups of the
+// same XCD (workgroup w runs on XCD w % 8), so neighbouring tiles -- which
+// re-read each other's halo -- share an L2.
+void share_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
+                std::vector<mpd::Segment> &segs, std::vector<int> &wg_begin)
 {
     struct Tile {
         int grid, tx, ty, nz;
@@ -150,6 +194,21 @@ void default_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
         if (l < nwg) segs.insert(segs.end(), share[l].begin(), share[l].end());
     }
     wg_begin[nwg_all] = (int)segs.size();
+}
+
+// Default plan: the whole-tile plan unless its makespan exceeds the
+// contiguous-share plan's by more than the L2 gain of aligned marches.
+void default_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
+                  std::vector<mpd::Segment> &segs, std::vector<int> &wg_begin)
+{
+    std::vector<mpd::Segment> s2;
+    std::vector<int> w2;
+    share_plan(grids, tile, nwg, segs, wg_begin);
+    whole_tile_plan(grids, tile, nwg, s2, w2);
+    if (plan_makespan(s2, w2) * 10 <= plan_makespan(segs, wg_begin) * 11) {
+        segs.swap(s2);
+        wg_begin.swap(w2);
+    }
 }
 
 // A plan must cover every output tile of every grid over all its planes
@@ -666,7 +725,7 @@ int mpdata_occupancy(int32_t dtype, int32_t tile, int32_t bc, int32_t nonos, int
                      int32_t *cus)
 {
     if (dtype != MPDATA_FP64 && dtype != MPDATA_FP32) return MPDATA_EINVAL;
-    if (tile == 0) tile = default_tile(dtype);
+    if (tile == 0) tile = default_tile(dtype, bc);
     if (tile < 1 || tile > mpdata_tile_count()) return MPDATA_EINVAL;
     const int per = wg_per_cu(dtype, tile, bc == MPDATA_BC_OPEN, nonos != 0);
     const int c = device_cus();

@@ -85,10 +85,10 @@ template <typename T> __device__ __forceinline__ T donor(T l, T r, T c)
     return pos(c) * l + neg(c) * r;
 }
 
-// Reciprocal by the hardware estimate refined with Newton-Raphson steps
-// r <- r + r (1 - x r) (two for FP64, one for FP32), and a quotient with one
-// residual correction q <- q + r (n - d q).  Accurate to about one unit in
-// the last place for the positive, normal operands used here.
+// Reciprocal by the hardware estimate (v_rcp_f64 is good to about 2^-24,
+// v_rcp_f32 to 1 ulp) refined with Newton-Raphson steps r <- r + r (1 - x r):
+// two for FP64, one for FP32, which leaves it correctly rounded or within one
+// unit in the last place for the positive, normal operands used here.
 __device__ __forceinline__ double rcp_nr(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
@@ -105,11 +105,22 @@ __device__ __forceinline__ float rcp_nr(float x)
     return fmaf(r, e, r);
 }
 
-template <typename T> __device__ __forceinline__ T div_nr(T n, T d)
+// Quotient: a reciprocal good to a few ulps (v_rcp_f64 plus one
+// Newton-Raphson step; v_rcp_f32 alone is within 1 ulp) and one residual
+// correction q <- q + r (n - d q), which squares the relative error away.
+__device__ __forceinline__ double div_nr(double n, double d)
 {
-    const T r = rcp_nr(d);
-    const T q = n * r;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    const double q = n * r;
     return fma(fma(-d, q, n), r, q);
+}
+
+__device__ __forceinline__ float div_nr(float n, float d)
+{
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float q = n * r;
+    return fmaf(fmaf(-d, q, n), r, q);
 }
 
 template <typename T> struct Tiny;
@@ -536,7 +547,7 @@ __global__ __launch_bounds__(256) void step_donor(DonorArgs<T> a)
 const TileShape *tile_shapes(int *count)
 {
     static const TileShape shapes[] = {
-        {64, 16}, {32, 32}, {64, 8}, {32, 16}, {32, 24},
+        {64, 16}, {32, 32}, {64, 8}, {32, 16}, {32, 24}, {16, 16},
     };
     *count = (int)(sizeof(shapes) / sizeof(shapes[0]));
     return shapes;
@@ -559,6 +570,7 @@ template <typename T> const void *step_kernel_ptr(int tile, bool open, bool nono
     case 3: return pick<T, 64, 8>(open, nonos);
     case 4: return pick<T, 32, 16>(open, nonos);
     case 5: return pick<T, 32, 24>(open, nonos);
+    case 6: return pick<T, 16, 16>(open, nonos);
     default: return nullptr;
     }
 }
