@@ -87,20 +87,27 @@ int tiles_x(const mpdata_params &p, int tile) { return (p.nx + shape_of(tile).rx
 int tiles_y(const mpdata_params &p, int tile) { return (p.ny + shape_of(tile).ry - 5) / (shape_of(tile).ry - 4); }
 
 // Whole-tile plan: tile i (listed grid by grid, row by row) marches all its
-// planes on workgroup i mod nwg.  Every workgroup starts its k-th tile at the
+// planes on one workgroup; tiles are dealt round-robin over the workgroups.  Every workgroup starts its k-th tile at the
 // same time and plane as its neighbours, so the halo lines that adjacent
 // tiles share are fetched once into L2 while both use them (measured: about
 // 15 % faster per march iteration than unaligned marches).
 void whole_tile_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
                      std::vector<mpd::Segment> &segs, std::vector<int> &wg_begin)
 {
+    // logical slot l = i mod nwg; slots [x*per_xcd, (x+1)*per_xcd) run on
+    // XCD x, so runs of consecutive tiles (row neighbours, and most column
+    // neighbours) share an L2
+    const int per_xcd = nwg % kXcds == 0 ? nwg / kXcds : 0;
     std::vector<std::vector<mpd::Segment>> per(nwg);
     int i = 0;
     for (int g = 0; g < (int)grids.size(); ++g) {
         const int ntx = tiles_x(grids[g], tile), nty = tiles_y(grids[g], tile);
         for (int ty = 0; ty < nty; ++ty)
-            for (int tx = 0; tx < ntx; ++tx, ++i)
-                per[i % nwg].push_back(mpd::Segment{g, tx, ty, 0, grids[g].nz, 0, 0, 0});
+            for (int tx = 0; tx < ntx; ++tx, ++i) {
+                const int l = i % nwg;
+                const int w = per_xcd ? (l % per_xcd) * kXcds + l / per_xcd : l;
+                per[w].push_back(mpd::Segment{g, tx, ty, 0, grids[g].nz, 0, 0, 0});
+            }
     }
     segs.clear();
     wg_begin.assign(nwg + 1, 0);
