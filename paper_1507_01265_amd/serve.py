@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import sys
 import time
 
 import numpy as np
@@ -226,7 +227,8 @@ class Server:
             if log_every and time.perf_counter() - last_log > log_every:
                 last_log = time.perf_counter()
                 print(f"# serve t={now():.1f}s done={len(done)} members={len(members)} "
-                      f"queued={len(sched.queue)} pending={len(pending)}", flush=True)
+                      f"queued={len(sched.queue)} pending={len(pending)}", file=sys.stderr,
+                      flush=True)
         self.elapsed = now()
         self.stats["admission_waits"] = sched.waits
         self.stats["peak_bytes"] = int(sched.peak)
