@@ -178,6 +178,17 @@ template <typename T> __device__ __forceinline__ T ld(gptr<const T> base, unsign
     return *(gptr<const T>)((__attribute__((address_space(1))) const char *)base + byte_off);
 }
 
+// A loop-invariant per-lane offset made opaque at its point of use (an empty
+// asm statement, no instruction), so the compiler keeps it as a 32-bit
+// register instead of hoisting a 64-bit extension of it out of the loop --
+// which would rule out the scalar-base + 32-bit-offset load form and cost
+// two registers per offset.
+__device__ __forceinline__ unsigned at_use(unsigned v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // Registers of one plane of a column: the Courant numbers of its x- and
 // y-faces and h (needed one iteration ahead) ...
 template <typename T> struct PlaneA {
@@ -245,16 +256,17 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     const unsigned o_u2hi = face_hi<OPEN>(gy, ny) * nx + cx;
     const bool has_rx = (lx == 0) || (lx == RX - 1);
     const bool has_ry = (ly == 0) || (ly == RY - 1);
-    const unsigned o_rx = cy * nx + cell_of<OPEN>(lx == 0 ? gx - 1 : gx + 1, nx);
-    const unsigned o_ry = cell_of<OPEN>(ly == 0 ? gy - 1 : gy + 1, ny) * nx + cx;
+    // ring cells of the psi^n plane (lanes off the ring re-read their own cell)
+    const unsigned o_rx = has_rx ? cy * nx + cell_of<OPEN>(lx == 0 ? gx - 1 : gx + 1, nx) : o_c;
+    const unsigned o_ry = has_ry ? cell_of<OPEN>(ly == 0 ? gy - 1 : gy + 1, ny) * nx + cx : o_c;
     // byte offsets within a plane (a plane of any array stays below 4 GiB:
     // the host limits every array to 2^31 elements)
     const unsigned b_c = o_c * (unsigned)sizeof(T);
     const unsigned b_u1lo = o_u1lo * (unsigned)sizeof(T), b_u1hi = o_u1hi * (unsigned)sizeof(T);
     const unsigned b_u2lo = o_u2lo * (unsigned)sizeof(T), b_u2hi = o_u2hi * (unsigned)sizeof(T);
     const unsigned b_rx = o_rx * (unsigned)sizeof(T), b_ry = o_ry * (unsigned)sizeof(T);
-    const int p_rx = q + (lx == 0 ? XM : XP);
-    const int p_ry = q + (ly == 0 ? YM : YP);
+    const int p_rx = has_rx ? q + (lx == 0 ? XM : XP) : q;
+    const int p_ry = has_ry ? q + (ly == 0 ? YM : YP) : q;
 
     // cell-centred neighbour offsets: at an open boundary a read of the cell
     // beyond it is redirected to the cell itself (zero gradient)
@@ -280,24 +292,26 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         const gptr<const T> hp = gh + (size_t)k * pc_cells;
         const gptr<const T> u1p = gu1 + (size_t)k * pc_u1;
         const gptr<const T> u2p = gu2 + (size_t)k * pc_u2;
-        r.h = ld(hp, b_c);
-        r.u1lo = ld(u1p, b_u1lo);
-        r.u1hi = ld(u1p, b_u1hi);
-        r.u2lo = ld(u2p, b_u2lo);
-        r.u2hi = ld(u2p, b_u2hi);
+        r.h = ld(hp, at_use(b_c));
+        r.u1lo = ld(u1p, at_use(b_u1lo));
+        r.u1hi = ld(u1p, at_use(b_u1hi));
+        r.u2lo = ld(u2p, at_use(b_u2lo));
+        r.u2hi = ld(u2p, at_use(b_u2hi));
     };
     auto load_b = [&](int k, int kf, PlaneB<T> &r) {
         const gptr<const T> pp = psi_in + (size_t)k * pc_cells;
         const gptr<const T> u3p = gu3 + (size_t)kf * pc_cells;
-        r.pn = ld(pp, b_c);
-        r.u3lo = ld(u3p, b_c);
-        r.ringx = has_rx ? ld(pp, b_rx) : T(0);
-        r.ringy = has_ry ? ld(pp, b_ry) : T(0);
+        r.pn = ld(pp, at_use(b_c));
+        r.u3lo = ld(u3p, at_use(b_c));
+        r.ringx = ld(pp, at_use(b_rx));
+        r.ringy = ld(pp, at_use(b_ry));
     };
     auto store_ring = [&](const PlaneB<T> &r) {
+        // off the ring p_rx = p_ry = q and the ring values equal psi^n of the
+        // lane's own cell: the three stores then write one value to one slot
         sP[q] = r.pn;
-        if (has_rx) sP[p_rx] = r.ringx;
-        if (has_ry) sP[p_ry] = r.ringy;
+        sP[p_rx] = r.ringx;
+        sP[p_ry] = r.ringy;
     };
 
     const int t0 = z0 - 2, tend = z1 + 1;
@@ -440,7 +454,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
             const T fc1hi = sFC1[q + XP], fc2hi = sFC2[q + YP];
             const T res = p1_m2 - (((fc1hi - sFC1[q]) + (fc2hi - sFC2[q])) + (fc3_m1 - fc3_m2)) * rh_m2;
             if (is_out && t >= z0 + 2 && t <= tend)
-                *(gptr<T>)((__attribute__((address_space(1))) char *)(psi_out + (size_t)(t - 2) * pc_cells) + b_c) = res;
+                *(gptr<T>)((__attribute__((address_space(1))) char *)(psi_out + (size_t)(t - 2) * pc_cells) + at_use(b_c)) = res;
         }
 
         // ---- hand the planes to the next iteration
