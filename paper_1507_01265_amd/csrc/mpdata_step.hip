@@ -23,8 +23,10 @@
 //    cell on every side, so neighbour offsets are compile-time constants;
 //  * the stage pipeline is skewed in z: iteration t computes psi1 at plane
 //    t, V, the bounds and the limiter factors at plane t-1 (and V3 on face
-//    t), the limited fluxes and the output at plane t-2; the march is
-//    unrolled by three so the three psi1 planes sit in fixed LDS slots;
+//    t), the limited corrective fluxes at plane t-2 and the output at plane
+//    t-3, with three workgroup barriers per iteration (each LDS buffer is
+//    written in the phase after its last read); the march is unrolled by
+//    three so the three psi1 planes sit in fixed LDS slots;
 //  * psi^n and u3 of plane t+2 and the other inputs of plane t+1 are
 //    prefetched into registers.
 // Only psi^{n+1} is written to HBM: 5 array reads + 1 write per cell-step.
@@ -152,7 +154,17 @@ __device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi
     const T cross = (us * nBs) * dBt + (ut * nBt) * dBs;
     const T num = (c * nA) * P - (T(0.25) * U * dA) * cross;
     const T den = (hs * dA) * P;
-    return den >= Tiny<T>::v ? div_nr(num, den) : T(0);
+    if constexpr (sizeof(T) == 8) {
+        // FP64: the guard never fires on real data; divide unconditionally
+        // and select, with no branch around the division
+        const T v = div_nr(num, fmax(den, Tiny<T>::v));
+        return den >= Tiny<T>::v ? v : T(0);
+    } else {
+        // FP32: the guard fires wherever psi1 vanishes around the face (eps^3
+        // underflows), and waves lying wholly in such a region skip the
+        // division
+        return den >= Tiny<T>::v ? div_nr(num, den) : T(0);
+    }
 }
 
 // Limited pseudo-velocity; the factors are in limiter precision (double).
@@ -164,29 +176,36 @@ __device__ __forceinline__ T limited(T v, double bup_a, double bdn_a, double bup
     return cp * pos(v) + cn * neg(v);
 }
 
-// Pointers read from a grid descriptor are generic; marking them as global
-// memory makes the compiler emit global (not flat) loads, which do not share
-// the LDS wait counter.
-template <typename T> using gptr = __attribute__((address_space(1))) T *;
-template <typename T> __device__ __forceinline__ gptr<T> as_global(T *p) { return (gptr<T>)p; }
+// Global memory is read and written through buffer descriptors: one
+// descriptor per plane of an array (base = the plane's first element, size =
+// the plane's bytes, built in scalar registers) and a loop-invariant 32-bit
+// byte offset per lane.  No 64-bit address arithmetic per access, and an
+// offset past the plane reads zero instead of leaving the array.  The host
+// keeps every plane below 4 GiB.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
 
-// Element at a 32-bit byte offset from a workgroup-uniform base: the address
-// is base + zext(offset), which maps onto the scalar-base + vector-offset
-// form of the global loads (no 64-bit address arithmetic per load).
-template <typename T> __device__ __forceinline__ T ld(gptr<const T> base, unsigned byte_off)
+template <typename T> __device__ __forceinline__ Rsrc plane_rsrc(const T *base, size_t plane, unsigned plane_elems)
 {
-    return *(gptr<const T>)((__attribute__((address_space(1))) const char *)base + byte_off);
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(base + plane * plane_elems), 0,
+                                             (int)(plane_elems * (unsigned)sizeof(T)), kRsrcWord3);
 }
 
-// A loop-invariant per-lane offset made opaque at its point of use (an empty
-// asm statement, no instruction), so the compiler keeps it as a 32-bit
-// register instead of hoisting a 64-bit extension of it out of the loop --
-// which would rule out the scalar-base + 32-bit-offset load form and cost
-// two registers per offset.
-__device__ __forceinline__ unsigned at_use(unsigned v)
+template <typename T> __device__ __forceinline__ T bload(Rsrc r, unsigned byte_off)
 {
-    asm volatile("" : "+v"(v));
-    return v;
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+
+template <typename T> __device__ __forceinline__ void bstore(Rsrc r, unsigned byte_off, T v)
+{
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
+                                              r, (int)byte_off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
 }
 
 // Registers of one plane of a column: the Courant numbers of its x- and
@@ -233,10 +252,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const T eps = T(eps_d);
     const L eps_l = eps_d;
-    const gptr<const T> psi_in = as_global<const T>(g.psi[flip]);
-    const gptr<T> psi_out = as_global<T>(g.psi[1 - flip]);
-    const gptr<const T> gh = as_global<const T>(g.h), gu1 = as_global<const T>(g.u1);
-    const gptr<const T> gu2 = as_global<const T>(g.u2), gu3 = as_global<const T>(g.u3);
+    const T *psi_in = g.psi[flip];
+    T *psi_out = g.psi[1 - flip];
 
     const int tid = threadIdx.x;
     const int lx = tid % RX, ly = tid / RX;
@@ -246,9 +263,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
 
     // in-plane offsets into the global arrays
     const int cx = cell_of<OPEN>(gx, nx), cy = cell_of<OPEN>(gy, ny);
-    const size_t pc_cells = (size_t)nx * ny;
-    const size_t pc_u1 = (size_t)(nx + 1) * ny;
-    const size_t pc_u2 = (size_t)nx * (ny + 1);
+    const unsigned pc_cells = (unsigned)nx * ny;
+    const unsigned pc_u1 = (unsigned)(nx + 1) * ny;
+    const unsigned pc_u2 = (unsigned)nx * (ny + 1);
     const unsigned o_c = cy * nx + cx;
     const unsigned o_u1lo = cy * (nx + 1) + face_lo<OPEN>(gx, nx);
     const unsigned o_u1hi = cy * (nx + 1) + face_hi<OPEN>(gx, nx);
@@ -259,8 +276,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     // ring cells of the psi^n plane (lanes off the ring re-read their own cell)
     const unsigned o_rx = has_rx ? cy * nx + cell_of<OPEN>(lx == 0 ? gx - 1 : gx + 1, nx) : o_c;
     const unsigned o_ry = has_ry ? cell_of<OPEN>(ly == 0 ? gy - 1 : gy + 1, ny) * nx + cx : o_c;
-    // byte offsets within a plane (a plane of any array stays below 4 GiB:
-    // the host limits every array to 2^31 elements)
+    // byte offsets within a plane (the host keeps every plane below 4 GiB)
     const unsigned b_c = o_c * (unsigned)sizeof(T);
     const unsigned b_u1lo = o_u1lo * (unsigned)sizeof(T), b_u1hi = o_u1hi * (unsigned)sizeof(T);
     const unsigned b_u2lo = o_u2lo * (unsigned)sizeof(T), b_u2hi = o_u2hi * (unsigned)sizeof(T);
@@ -289,22 +305,22 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         return k + 1 == nz ? 0 : k + 1;
     };
     auto load_a = [&](int k, PlaneA<T> &r) {
-        const gptr<const T> hp = gh + (size_t)k * pc_cells;
-        const gptr<const T> u1p = gu1 + (size_t)k * pc_u1;
-        const gptr<const T> u2p = gu2 + (size_t)k * pc_u2;
-        r.h = ld(hp, at_use(b_c));
-        r.u1lo = ld(u1p, at_use(b_u1lo));
-        r.u1hi = ld(u1p, at_use(b_u1hi));
-        r.u2lo = ld(u2p, at_use(b_u2lo));
-        r.u2hi = ld(u2p, at_use(b_u2hi));
+        const Rsrc hp = plane_rsrc(g.h, k, pc_cells);
+        const Rsrc u1p = plane_rsrc(g.u1, k, pc_u1);
+        const Rsrc u2p = plane_rsrc(g.u2, k, pc_u2);
+        r.h = bload<T>(hp, b_c);
+        r.u1lo = bload<T>(u1p, b_u1lo);
+        r.u1hi = bload<T>(u1p, b_u1hi);
+        r.u2lo = bload<T>(u2p, b_u2lo);
+        r.u2hi = bload<T>(u2p, b_u2hi);
     };
     auto load_b = [&](int k, int kf, PlaneB<T> &r) {
-        const gptr<const T> pp = psi_in + (size_t)k * pc_cells;
-        const gptr<const T> u3p = gu3 + (size_t)kf * pc_cells;
-        r.pn = ld(pp, at_use(b_c));
-        r.u3lo = ld(u3p, at_use(b_c));
-        r.ringx = ld(pp, at_use(b_rx));
-        r.ringy = ld(pp, at_use(b_ry));
+        const Rsrc pp = plane_rsrc(psi_in, k, pc_cells);
+        const Rsrc u3p = plane_rsrc(g.u3, kf, pc_cells);
+        r.pn = bload<T>(pp, b_c);
+        r.u3lo = bload<T>(u3p, b_c);
+        r.ringx = bload<T>(pp, b_rx);
+        r.ringy = bload<T>(pp, b_ry);
     };
     auto store_ring = [&](const PlaneB<T> &r) {
         // off the ring p_rx = p_ry = q and the ring values equal psi^n of the
@@ -314,7 +330,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         sP[p_ry] = r.ringy;
     };
 
-    const int t0 = z0 - 2, tend = z1 + 1;
+    const int t0 = z0 - 2, tend = z1 + 2;
     // the march runs a multiple of three iterations; iterations past tend
     // only reload valid planes and store nothing
     const int tstop = t0 + ((tend - t0 + 1 + 2) / 3) * 3 - 1;
@@ -325,7 +341,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     load_a(plane_of(t0), curA);
     load_b(plane_of(t0), zface_of(t0), cur);
     load_b(ka, zface_of(t0 + 1), nx1);
-    const T pn_prev = ld(psi_in + (size_t)plane_of(t0 - 1) * pc_cells, b_c);
+    const T pn_prev = bload<T>(plane_rsrc(psi_in, plane_of(t0 - 1), pc_cells), b_c);
     store_ring(cur);
 
     // z-history of the column
@@ -333,23 +349,46 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     T pn_m1 = pn_prev, pn_m2 = T(0);
     T pmx_m1 = T(0), pmn_m1 = T(0);             // in-plane 5-point max/min of psi^n(t-1)
     T u1_m1 = T(0), u2_m1 = T(0);               // lower-face Courant, plane t-1
-    T rh_m1 = T(1), rh_m2 = T(1);               // 1/h of planes t-1, t-2
+    T rh_m1 = T(1), rh_m2 = T(1), rh_m3 = T(1); // 1/h of planes t-1 .. t-3
+    // Own-column psi1 of planes t-1 .. t-3 and the Courant sums and h of plane
+    // t-1 also sit in LDS; FP32 has the registers to keep a copy and save
+    // seven LDS reads per iteration, FP64 reads them back.
+    constexpr bool kHist = sizeof(T) == 4;
+    T r_p1_m1 = T(0), r_p1_m2 = T(0), r_p1_m3 = T(0);
+    T r_c1_m1 = T(0), r_c2_m1 = T(0), r_c3_m1 = T(0), r_h_m1 = T(0);
     T v1_m2 = T(0), v2_m2 = T(0), v3_m1 = T(0); // V at plane t-2, V3 at face t-1
     T fa3_m1 = T(0);                            // antidiffusive flux, face t-1
     L bu_m2 = 1.0, bd_m2 = 1.0;                 // limiter factors, plane t-2
-    T fc3_m2 = T(0);                            // corrective flux, face t-2
+    T fc3_m2 = T(0), fc3_m3 = T(0);             // corrective flux, faces t-2, t-3
 
     auto iter = [&](const int t, auto slot) {
-        constexpr int s0 = decltype(slot)::value;           // slot of plane t
+        constexpr int s0 = decltype(slot)::value;           // slot of plane t (held t-3)
         constexpr int s1 = (s0 + 2) % 3, s2 = (s0 + 1) % 3; // planes t-1, t-2
         load_a(ka, nxA);
         load_b(kb, OPEN ? zface_of(t + 2) : kb, nx2);
         ka = kb;
         kb = next_plane(kb, t + 3);
-        __syncthreads();  // (B) psi^n(t), sums/h of t-1 and beta of t-2 are visible
-        // own-column values of planes t-1 and t-2 that already sit in LDS
-        const T p1_m1 = sQ[s1][q], p1_m2 = sQ[s2][q];
-        const T c1_m1 = sC1[q], c2_m1 = sC2[q], c3_m1 = sC3[q], h_m1 = sH[q];
+        __syncthreads();  // (B) psi^n(t), sums/h of t-1, corrective fluxes of t-3 are visible
+        // own-column values of planes t-1 .. t-3 that already sit in LDS
+        const T p1_m1 = kHist ? r_p1_m1 : sQ[s1][q], p1_m2 = kHist ? r_p1_m2 : sQ[s2][q];
+        const T p1_m3 = kHist ? r_p1_m3 : sQ[s0][q];
+        const T c1_m1 = kHist ? r_c1_m1 : sC1[q], c2_m1 = kHist ? r_c2_m1 : sC2[q];
+        const T c3_m1 = kHist ? r_c3_m1 : sC3[q], h_m1 = kHist ? r_h_m1 : sH[q];
+
+        // limiter factors of plane t-2 (computed last iteration) for the
+        // neighbours' corrective pass after (F); their previous contents were
+        // last read before (B)
+        if (NONOS) {
+            sBU[q] = bu_m2;
+            sBD[q] = bd_m2;
+        }
+        {
+            // ---- S7 at plane t-3 (its corrective fluxes were stored last iteration)
+            const T fc1hi = sFC1[q + XP], fc2hi = sFC2[q + YP];
+            const T res = p1_m3 - (((fc1hi - sFC1[q]) + (fc2hi - sFC2[q])) + (fc3_m2 - fc3_m3)) * rh_m3;
+            if (is_out && t >= z0 + 3 && t <= tend)
+                bstore<T>(plane_rsrc<T>(psi_out, t - 3, pc_cells), b_c, res);
+        }
 
         // ---- S1+S2 at plane t
         const T pL = sP[q + cxm], pR = sP[q + cxp];
@@ -361,11 +400,11 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         const T p1_c = cur.pn - (((f1hi - f1lo) + (f2hi - f2lo)) + (f3hi - f3_c)) * rh_c;
         const T pmx_c = fmax(fmax(fmax(pL, pR), fmax(pD, pU)), cur.pn);
         const T pmn_c = fmin(fmin(fmin(pL, pR), fmin(pD, pU)), cur.pn);
-        sQ[s0][q] = p1_c;
+        sQ[s0][q] = p1_c;  // psi1(t-3) of this slot was last read before (B)
         const T c1_c = curA.u1lo + curA.u1hi;
         const T c2_c = curA.u2lo + curA.u2hi;
         const T c3_c = cur.u3lo + nx1.u3lo;
-        __syncthreads();  // (D) psi1(t) visible
+        __syncthreads();  // (D) psi1(t) and the limiter factors of t-2 are visible
 
         T v1, v2, v3, fa3_c = T(0);
         T mx = T(0), mn = T(0);
@@ -412,6 +451,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
                 fa3_c = donor(p1_m1, p1_c, v3);
             }
         }
+        // psi^n of plane t+1: every read of plane t in sP happened before (D)
+        store_ring(nx1);
         __syncthreads();  // (F) antidiffusive fluxes visible
 
         L bu_m1 = 1.0, bd_m1 = 1.0;
@@ -432,7 +473,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
 
         T fc3_m1;
         {
-            // ---- S6 + corrective fluxes at plane r = t-2 (lower faces) and on face t-1
+            // ---- S6 + corrective fluxes at plane r = t-2 (lower faces) and on face t-1;
+            // the fluxes of t-3 in sFC were read before (D)
             const T *Qr = sQ[s2];
             T vt1 = v1_m2, vt2 = v2_m2, vt3 = v3_m1;
             if (NONOS) {
@@ -447,33 +489,21 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
             sFC2[q] = donor(Qr[q + YM], p1_m2, vt2);
             fc3_m1 = donor(p1_m2, p1_m1, vt3);
         }
-        __syncthreads();  // (J) corrective fluxes visible
-
-        {
-            // ---- S7 at plane r = t-2
-            const T fc1hi = sFC1[q + XP], fc2hi = sFC2[q + YP];
-            const T res = p1_m2 - (((fc1hi - sFC1[q]) + (fc2hi - sFC2[q])) + (fc3_m1 - fc3_m2)) * rh_m2;
-            if (is_out && t >= z0 + 2 && t <= tend)
-                *(gptr<T>)((__attribute__((address_space(1))) char *)(psi_out + (size_t)(t - 2) * pc_cells) + at_use(b_c)) = res;
-        }
-
-        // ---- hand the planes to the next iteration
-        if (NONOS) {
-            sBU[q] = bu_m1;
-            sBD[q] = bd_m1;
-        }
+        // sums/h of plane t for the next iteration: the reads of plane t-1
+        // happened before (F)
         sC1[q] = c1_c;
         sC2[q] = c2_c;
         sC3[q] = c3_c;
         sH[q] = curA.h;
-        store_ring(nx1);
 
+        // ---- hand the planes to the next iteration
         pn_m2 = pn_m1;
         pn_m1 = cur.pn;
         pmx_m1 = pmx_c;
         pmn_m1 = pmn_c;
         u1_m1 = curA.u1lo;
         u2_m1 = curA.u2lo;
+        rh_m3 = rh_m2;
         rh_m2 = rh_m1;
         rh_m1 = rh_c;
         f3_c = f3hi;
@@ -483,7 +513,17 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         fa3_m1 = fa3_c;
         bu_m2 = bu_m1;
         bd_m2 = bd_m1;
+        fc3_m3 = fc3_m2;
         fc3_m2 = fc3_m1;
+        if (kHist) {
+            r_p1_m3 = p1_m2;
+            r_p1_m2 = p1_m1;
+            r_p1_m1 = p1_c;
+            r_c1_m1 = c1_c;
+            r_c2_m1 = c2_c;
+            r_c3_m1 = c3_c;
+            r_h_m1 = curA.h;
+        }
         curA = nxA;
         cur = nx1;
         nx1 = nx2;

@@ -59,7 +59,8 @@ def test_workspace_bytes():
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(nz=-1), dict(dtype=2), dict(bc=5),
                                  dict(iord=3), dict(iord=1, nonos=1), dict(nonos=2),
                                  dict(eps=0.0), dict(eps=float("nan")), dict(tile=99),
-                                 dict(nx=4096, ny=4096, nz=256)])
+                                 dict(nx=4096, ny=4096, nz=256),
+                                 dict(nx=30000, ny=30000, nz=1)])
 def test_invalid_params_are_rejected(bad):
     p = _params(**bad)
     assert _lib.mpdata_workspace_bytes(p) == 0
@@ -67,6 +68,13 @@ def test_invalid_params_are_rejected(bad):
         _lib.mpdata_create(p, 256, 256, 256, 256, 256, 256, 1 << 30, None)
     assert e.value.code == _lib.MPDATA_EINVAL
     assert _lib.mpdata_last_error(None)
+
+
+def test_plane_limit_depends_on_word_size():
+    # one x-y plane is addressed with 32-bit byte offsets: 30001^2 words fit
+    # in 4 GiB as FP32, not as FP64
+    assert _lib.mpdata_workspace_bytes(_params(nx=30000, ny=30000, nz=1, dtype=1)) > 0
+    assert _lib.mpdata_workspace_bytes(_params(nx=30000, ny=30000, nz=1, dtype=0)) == 0
 
 
 def test_null_and_misaligned_pointers_are_rejected():
