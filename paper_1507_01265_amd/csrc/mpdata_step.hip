@@ -213,10 +213,10 @@ template <typename T> __device__ __forceinline__ void bstore(Rsrc r, unsigned by
 template <typename T> struct PlaneA {
     T u1lo, u1hi, u2lo, u2hi, h;
 };
-// ... and psi^n, the Courant number of its lower z-face and the LDS ring of
-// psi^n (needed two iterations ahead).
+// ... and psi^n, the Courant number of its lower z-face and (threads that
+// load it) one cell of the LDS ring of psi^n (needed two iterations ahead).
 template <typename T> struct PlaneB {
-    T pn, u3lo, ringx, ringy;
+    T pn, u3lo, ring;
 };
 
 // ================================================================ fused step
@@ -271,18 +271,30 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     const unsigned o_u1hi = cy * (nx + 1) + face_hi<OPEN>(gx, nx);
     const unsigned o_u2lo = face_lo<OPEN>(gy, ny) * nx + cx;
     const unsigned o_u2hi = face_hi<OPEN>(gy, ny) * nx + cx;
-    const bool has_rx = (lx == 0) || (lx == RX - 1);
-    const bool has_ry = (ly == 0) || (ly == RY - 1);
-    // ring cells of the psi^n plane (lanes off the ring re-read their own cell)
-    const unsigned o_rx = has_rx ? cy * nx + cell_of<OPEN>(lx == 0 ? gx - 1 : gx + 1, nx) : o_c;
-    const unsigned o_ry = has_ry ? cell_of<OPEN>(ly == 0 ? gy - 1 : gy + 1, ny) * nx + cx : o_c;
+    // The ring of the psi^n plane -- the padded LDS cells around the region,
+    // 2 RY of them left and right, 2 RX below and above -- is loaded by the
+    // first 2 (RX + RY) threads, one cell each (the other waves skip it).
+    constexpr int NRX = 2 * RY, NR = 2 * (RX + RY);
+    static_assert(NR <= RX * RY, "ring larger than the workgroup");
+    const bool has_ring = tid < NR;
+    int rgx = gx, rgy = gy, p_ring = q;
+    if (tid < NRX) {
+        const int side = tid / RY, row = tid % RY;
+        rgx = tx * TX - 2 + (side ? RX : -1);
+        rgy = ty * TY - 2 + row;
+        p_ring = (row + 1) * PX + (side ? RX + 1 : 0);
+    } else if (has_ring) {
+        const int side = (tid - NRX) / RX, col = (tid - NRX) % RX;
+        rgx = tx * TX - 2 + col;
+        rgy = ty * TY - 2 + (side ? RY : -1);
+        p_ring = (side ? RY + 1 : 0) * PX + col + 1;
+    }
+    const unsigned o_ring = cell_of<OPEN>(rgy, ny) * nx + cell_of<OPEN>(rgx, nx);
     // byte offsets within a plane (the host keeps every plane below 4 GiB)
     const unsigned b_c = o_c * (unsigned)sizeof(T);
     const unsigned b_u1lo = o_u1lo * (unsigned)sizeof(T), b_u1hi = o_u1hi * (unsigned)sizeof(T);
     const unsigned b_u2lo = o_u2lo * (unsigned)sizeof(T), b_u2hi = o_u2hi * (unsigned)sizeof(T);
-    const unsigned b_rx = o_rx * (unsigned)sizeof(T), b_ry = o_ry * (unsigned)sizeof(T);
-    const int p_rx = has_rx ? q + (lx == 0 ? XM : XP) : q;
-    const int p_ry = has_ry ? q + (ly == 0 ? YM : YP) : q;
+    const unsigned b_ring = o_ring * (unsigned)sizeof(T);
 
     // cell-centred neighbour offsets: at an open boundary a read of the cell
     // beyond it is redirected to the cell itself (zero gradient)
@@ -319,15 +331,11 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         const Rsrc u3p = plane_rsrc(g.u3, kf, pc_cells);
         r.pn = bload<T>(pp, b_c);
         r.u3lo = bload<T>(u3p, b_c);
-        r.ringx = bload<T>(pp, b_rx);
-        r.ringy = bload<T>(pp, b_ry);
+        r.ring = has_ring ? bload<T>(pp, b_ring) : T(0);
     };
     auto store_ring = [&](const PlaneB<T> &r) {
-        // off the ring p_rx = p_ry = q and the ring values equal psi^n of the
-        // lane's own cell: the three stores then write one value to one slot
         sP[q] = r.pn;
-        sP[p_rx] = r.ringx;
-        sP[p_ry] = r.ringy;
+        if (has_ring) sP[p_ring] = r.ring;
     };
 
     const int t0 = z0 - 2, tend = z1 + 2;
@@ -429,11 +437,15 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
                                  sC3[q + XM] + c3_m1, p1_hi + Qhi[q + XM], p1_lo + Qlo[q + XM],
                                  eps);
             if (zero_v1) v1 = T(0);
+            // the three faces are scheduled one after another: each face's
+            // temporaries die before the next face's LDS reads are issued
+            __builtin_amdgcn_sched_barrier(0);
             // y-face between a = (ly-1) and b = own; transverse axes z then x
             v2 = pseudo_velocity(u2_m1, sH[q + YM] + h_m1, qd, p1_m1, sC3[q + YM] + c3_m1,
                                  p1_hi + Qhi[q + YM], p1_lo + Qlo[q + YM], sC1[q + YM] + c1_m1,
                                  qxp_ + Qc[q + YM + cxp], qxm_ + Qc[q + YM + cxm], eps);
             if (zero_v2) v2 = T(0);
+            __builtin_amdgcn_sched_barrier(0);
             // z-face t between a = plane t-1 and b = plane t; transverse x then y
             v3 = pseudo_velocity(cur.u3lo, h_m1 + curA.h, p1_m1, p1_c, c1_m1 + c1_c,
                                  Qb[q + cxp] + qxp_, Qb[q + cxm] + qxm_, c2_m1 + c2_c,
