@@ -191,12 +191,13 @@ template <typename T> __device__ __forceinline__ Rsrc plane_rsrc(const T *base, 
                                              (int)(plane_elems * (unsigned)sizeof(T)), kRsrcWord3);
 }
 
-template <typename T> __device__ __forceinline__ T bload(Rsrc r, unsigned byte_off)
+// byte_off: per-lane offset; s_off: workgroup-uniform offset added to it
+template <typename T> __device__ __forceinline__ T bload(Rsrc r, unsigned byte_off, unsigned s_off = 0)
 {
     if constexpr (sizeof(T) == 8)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, (int)s_off, 0));
     else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, (int)s_off, 0));
 }
 
 template <typename T> __device__ __forceinline__ void bstore(Rsrc r, unsigned byte_off, T v)
@@ -208,15 +209,50 @@ template <typename T> __device__ __forceinline__ void bstore(Rsrc r, unsigned by
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
 }
 
+// Lane exchange along x inside a wave.  A workgroup's rows are RX lanes long
+// and RX divides 64 or is 64, so the x-neighbours of a lane are the adjacent
+// lanes of its wave: from_lo(v) is v of lane i-1, from_hi(v) v of lane i+1
+// (DPP wave shifts).  The first and last lane of a row receive a value from
+// another row (or 0); they hold the outermost halo columns of the region,
+// and no output depends on what they compute from it.
+//
+// A DPP move reads its source from the other lanes only where those lanes
+// are active, so it must run with the full exec mask: every exchange is a
+// statement of its own in the uniform march (never an arm of a conditional
+// expression, which runs for the selected lanes only), and its result is
+// pinned there by an empty asm statement so that it is not sunk into a
+// lane-masked region either.
+constexpr int kDppWaveShr1 = 0x138, kDppWaveShl1 = 0x130;
+
+template <int CTRL> __device__ __forceinline__ float dpp(float v)
+{
+    float r = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+    asm volatile("" : "+v"(r));
+    return r;
+}
+
+template <int CTRL> __device__ __forceinline__ double dpp(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+    double r = __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+    asm volatile("" : "+v"(r));
+    return r;
+}
+
+template <typename T> __device__ __forceinline__ T from_lo(T v) { return dpp<kDppWaveShr1>(v); }
+template <typename T> __device__ __forceinline__ T from_hi(T v) { return dpp<kDppWaveShl1>(v); }
+
 // Registers of one plane of a column: the Courant numbers of its x- and
 // y-faces and h (needed one iteration ahead) ...
 template <typename T> struct PlaneA {
     T u1lo, u1hi, u2lo, u2hi, h;
 };
-// ... and psi^n, the Courant number of its lower z-face and (threads that
-// load it) one cell of the LDS ring of psi^n (needed two iterations ahead).
+// ... and psi^n and the Courant number of its lower z-face (needed two
+// iterations ahead).
 template <typename T> struct PlaneB {
-    T pn, u3lo, ring;
+    T pn, u3lo;
 };
 
 // ================================================================ fused step
@@ -227,9 +263,12 @@ template <typename T, int RX, int RY> struct Smem {
     T sP[PP];                            // psi^n plane t (its ring holds real data)
     T sQ[3][PP];                         // psi1, planes t-2 .. t in fixed slots
     T sC1[PP], sC2[PP], sC3[PP], sH[PP]; // Courant column sums, h: plane t-1
-    T sFA1[PP], sFA2[PP];                // antidiffusive donor fluxes, lower faces
+    // x-face fluxes go through LDS only where x-neighbours are not
+    // exchanged between lanes (FP32)
+    static constexpr int PX1 = sizeof(T) == 8 ? 1 : PP;
+    T sFA1[PX1], sFA2[PP];               // antidiffusive donor fluxes, lower faces
     double sBU[PP], sBD[PP];             // limiter factors, plane t-2
-    T sFC1[PP], sFC2[PP];                // corrective fluxes, lower faces
+    T sFC1[PX1], sFC2[PP];               // corrective fluxes, lower faces
 };
 
 // One workgroup advances the output tile (tx, ty) of grid g through planes
@@ -298,8 +337,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
 
     // cell-centred neighbour offsets: at an open boundary a read of the cell
     // beyond it is redirected to the cell itself (zero gradient)
-    const int cxm = (OPEN && gx <= 0) ? 0 : XM;
-    const int cxp = (OPEN && gx >= nx - 1) ? 0 : XP;
+    const bool edge_lo = OPEN && gx <= 0, edge_hi = OPEN && gx >= nx - 1;
+    const int cxm = edge_lo ? 0 : XM;
+    const int cxp = edge_hi ? 0 : XP;
     const int cym = (OPEN && gy <= 0) ? 0 : YM;
     const int cyp = (OPEN && gy >= ny - 1) ? 0 : YP;
 
@@ -322,20 +362,29 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         const Rsrc u2p = plane_rsrc(g.u2, k, pc_u2);
         r.h = bload<T>(hp, b_c);
         r.u1lo = bload<T>(u1p, b_u1lo);
-        r.u1hi = bload<T>(u1p, b_u1hi);
-        r.u2lo = bload<T>(u2p, b_u2lo);
-        r.u2hi = bload<T>(u2p, b_u2hi);
+        if (OPEN) {
+            r.u1hi = bload<T>(u1p, b_u1hi);
+            r.u2lo = bload<T>(u2p, b_u2lo);
+            r.u2hi = bload<T>(u2p, b_u2hi);
+        } else {
+            // periodic: the upper faces are the next face along the axis and
+            // the lower y-face has the cell's own index, so no offsets of
+            // their own are held
+            r.u1hi = bload<T>(u1p, b_u1lo + (unsigned)sizeof(T));
+            r.u2lo = bload<T>(u2p, b_c);
+            r.u2hi = bload<T>(u2p, b_c, (unsigned)nx * (unsigned)sizeof(T));
+        }
     };
     auto load_b = [&](int k, int kf, PlaneB<T> &r) {
         const Rsrc pp = plane_rsrc(psi_in, k, pc_cells);
         const Rsrc u3p = plane_rsrc(g.u3, kf, pc_cells);
         r.pn = bload<T>(pp, b_c);
         r.u3lo = bload<T>(u3p, b_c);
-        r.ring = has_ring ? bload<T>(pp, b_ring) : T(0);
     };
-    auto store_ring = [&](const PlaneB<T> &r) {
-        sP[q] = r.pn;
-        if (has_ring) sP[p_ring] = r.ring;
+    // The ring threads load their ring cell of a plane late in the
+    // iteration before it is stored (it is not held across the heavy phase).
+    auto load_ring = [&](int k) {
+        return has_ring ? bload<T>(plane_rsrc(psi_in, k, pc_cells), b_ring) : T(0);
     };
 
     const int t0 = z0 - 2, tend = z1 + 2;
@@ -350,24 +399,32 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     load_b(plane_of(t0), zface_of(t0), cur);
     load_b(ka, zface_of(t0 + 1), nx1);
     const T pn_prev = bload<T>(plane_rsrc(psi_in, plane_of(t0 - 1), pc_cells), b_c);
-    store_ring(cur);
+    sP[q] = cur.pn;
+    if (has_ring) sP[p_ring] = load_ring(plane_of(t0));
+    T rng = load_ring(ka);  // ring cell of plane t+1
 
     // z-history of the column
     T f3_c = donor(pn_prev, cur.pn, cur.u3lo);  // psi^n flux, face t
-    T pn_m1 = pn_prev, pn_m2 = T(0);
-    T pmx_m1 = T(0), pmn_m1 = T(0);             // in-plane 5-point max/min of psi^n(t-1)
+    T pn_m1 = pn_prev;
+    // max/min of psi^n over the in-plane 5-point stencil of plane t-1 and the
+    // plane below it: the bounds at t-1 add only psi^n(t) to these
+    T zmx_m1 = T(0), zmn_m1 = T(0);
     T u1_m1 = T(0), u2_m1 = T(0);               // lower-face Courant, plane t-1
     T rh_m1 = T(1), rh_m2 = T(1), rh_m3 = T(1); // 1/h of planes t-1 .. t-3
     // Own-column psi1 of planes t-1 .. t-3 and the Courant sums and h of plane
     // t-1 also sit in LDS; FP32 has the registers to keep a copy and save
     // seven LDS reads per iteration, FP64 reads them back.
     constexpr bool kHist = sizeof(T) == 4;
+    // x-neighbours by lane exchange (FP64, where LDS bandwidth binds) or
+    // through LDS (FP32, where the exchange costs more issue than it saves)
+    constexpr bool kDpp = sizeof(T) == 8;
     T r_p1_m1 = T(0), r_p1_m2 = T(0), r_p1_m3 = T(0);
     T r_c1_m1 = T(0), r_c2_m1 = T(0), r_c3_m1 = T(0), r_h_m1 = T(0);
     T v1_m2 = T(0), v2_m2 = T(0), v3_m1 = T(0); // V at plane t-2, V3 at face t-1
     T fa3_m1 = T(0);                            // antidiffusive flux, face t-1
     L bu_m2 = 1.0, bd_m2 = 1.0;                 // limiter factors, plane t-2
     T fc3_m2 = T(0), fc3_m3 = T(0);             // corrective flux, faces t-2, t-3
+    T fc1_m3 = T(0), fc2_m3 = T(0);             // corrective fluxes, lower x/y faces of plane t-3
 
     auto iter = [&](const int t, auto slot) {
         constexpr int s0 = decltype(slot)::value;           // slot of plane t (held t-3)
@@ -376,7 +433,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         load_b(kb, OPEN ? zface_of(t + 2) : kb, nx2);
         ka = kb;
         kb = next_plane(kb, t + 3);
-        __syncthreads();  // (B) psi^n(t), sums/h of t-1, corrective fluxes of t-3 are visible
+        __syncthreads();  // (B) psi^n(t), sums/h of t-1, corrective y-fluxes of t-3 are visible
         // own-column values of planes t-1 .. t-3 that already sit in LDS
         const T p1_m1 = kHist ? r_p1_m1 : sQ[s1][q], p1_m2 = kHist ? r_p1_m2 : sQ[s2][q];
         const T p1_m3 = kHist ? r_p1_m3 : sQ[s0][q];
@@ -392,8 +449,12 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         }
         {
             // ---- S7 at plane t-3 (its corrective fluxes were stored last iteration)
-            const T fc1hi = sFC1[q + XP], fc2hi = sFC2[q + YP];
-            const T res = p1_m3 - (((fc1hi - sFC1[q]) + (fc2hi - sFC2[q])) + (fc3_m2 - fc3_m3)) * rh_m3;
+            T fc1hi;
+            if constexpr (kDpp) fc1hi = from_hi(fc1_m3);
+            else fc1hi = sFC1[q + XP];
+            const T fc2hi = sFC2[q + YP];
+            const T fc2lo = kHist ? fc2_m3 : sFC2[q];
+            const T res = p1_m3 - (((fc1hi - fc1_m3) + (fc2hi - fc2lo)) + (fc3_m2 - fc3_m3)) * rh_m3;
             if (is_out && t >= z0 + 3 && t <= tend)
                 bstore<T>(plane_rsrc<T>(psi_out, t - 3, pc_cells), b_c, res);
         }
@@ -406,15 +467,17 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         const T f3hi = donor(cur.pn, nx1.pn, nx1.u3lo);
         const T rh_c = rcp_nr(curA.h);
         const T p1_c = cur.pn - (((f1hi - f1lo) + (f2hi - f2lo)) + (f3hi - f3_c)) * rh_c;
-        const T pmx_c = fmax(fmax(fmax(pL, pR), fmax(pD, pU)), cur.pn);
-        const T pmn_c = fmin(fmin(fmin(pL, pR), fmin(pD, pU)), cur.pn);
+        // (at an open bottom the plane below t is t itself, already counted)
+        const bool zlo = OPEN && t <= 0;
+        const T zmx_c = fmax(fmax(fmax(pL, pR), fmax(pD, pU)), zlo ? cur.pn : fmax(cur.pn, pn_m1));
+        const T zmn_c = fmin(fmin(fmin(pL, pR), fmin(pD, pU)), zlo ? cur.pn : fmin(cur.pn, pn_m1));
         sQ[s0][q] = p1_c;  // psi1(t-3) of this slot was last read before (B)
         const T c1_c = curA.u1lo + curA.u1hi;
         const T c2_c = curA.u2lo + curA.u2hi;
         const T c3_c = cur.u3lo + nx1.u3lo;
         __syncthreads();  // (D) psi1(t) and the limiter factors of t-2 are visible
 
-        T v1, v2, v3, fa3_c = T(0);
+        T v1, v2, v3, fa1 = T(0), fa2 = T(0), fa3_c = T(0);
         T mx = T(0), mn = T(0);
         {
             // ---- S3 at plane p = t-1 (lower x- and y-faces) and on face t
@@ -427,51 +490,102 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
             const T p1_lo = clo ? p1_m1 : p1_m2;
             const T p1_hi = chi ? p1_m1 : p1_c;
 
-            const T qa = Qc[q + XM];  // cell a of the lower x-face
+            // y-neighbours from LDS; x-neighbours from the adjacent lanes
+            // (FP64) or from LDS (FP32); at an open x-boundary the cell
+            // beyond is the cell itself
             const T qd = Qc[q + YM];  // cell a of the lower y-face
             const T qyp_ = Qc[q + cyp], qym_ = Qc[q + cym];
-            const T qxp_ = Qc[q + cxp], qxm_ = Qc[q + cxm];
-            // x-face between a = (lx-1) and b = own; transverse axes y then z
-            v1 = pseudo_velocity(u1_m1, sH[q + XM] + h_m1, qa, p1_m1, sC2[q + XM] + c2_m1,
-                                 qyp_ + Qc[q + XM + cyp], qym_ + Qc[q + XM + cym],
-                                 sC3[q + XM] + c3_m1, p1_hi + Qhi[q + XM], p1_lo + Qlo[q + XM],
-                                 eps);
-            if (zero_v1) v1 = T(0);
+            T qa, qxp_, qxm_;         // qa: cell a of the lower x-face
+            if constexpr (kDpp) {
+                qa = from_lo(p1_m1);
+                const T p1_xhi = from_hi(p1_m1);
+                qxp_ = edge_hi ? p1_m1 : p1_xhi;
+                qxm_ = edge_lo ? p1_m1 : qa;
+            } else {
+                qa = Qc[q + XM];
+                qxp_ = Qc[q + cxp];
+                qxm_ = Qc[q + cxm];
+            }
+            {
+                // x-face between a = (lx-1) and b = own; transverse axes y then z
+                T h_a, c2_a, c3_a, qyp_a, qym_a, phi_a, plo_a;
+                if constexpr (kDpp) {
+                    h_a = from_lo(h_m1), c2_a = from_lo(c2_m1), c3_a = from_lo(c3_m1);
+                    qyp_a = from_lo(qyp_), qym_a = from_lo(qym_);
+                    phi_a = from_lo(p1_hi), plo_a = from_lo(p1_lo);
+                } else {
+                    h_a = sH[q + XM], c2_a = sC2[q + XM], c3_a = sC3[q + XM];
+                    qyp_a = Qc[q + XM + cyp], qym_a = Qc[q + XM + cym];
+                    phi_a = Qhi[q + XM], plo_a = Qlo[q + XM];
+                }
+                v1 = pseudo_velocity(u1_m1, h_a + h_m1, qa, p1_m1, c2_a + c2_m1, qyp_ + qyp_a,
+                                     qym_ + qym_a, c3_a + c3_m1, p1_hi + phi_a, p1_lo + plo_a, eps);
+                if (zero_v1) v1 = T(0);
+            }
             // the three faces are scheduled one after another: each face's
-            // temporaries die before the next face's LDS reads are issued
+            // temporaries die before the next face's reads are issued
             __builtin_amdgcn_sched_barrier(0);
-            // y-face between a = (ly-1) and b = own; transverse axes z then x
-            v2 = pseudo_velocity(u2_m1, sH[q + YM] + h_m1, qd, p1_m1, sC3[q + YM] + c3_m1,
-                                 p1_hi + Qhi[q + YM], p1_lo + Qlo[q + YM], sC1[q + YM] + c1_m1,
-                                 qxp_ + Qc[q + YM + cxp], qxm_ + Qc[q + YM + cxm], eps);
-            if (zero_v2) v2 = T(0);
+            {
+                // y-face between a = (ly-1) and b = own; transverse axes z then x
+                T qd_xp, qd_xm;
+                if constexpr (kDpp) {
+                    const T xhi = from_hi(qd), xlo = from_lo(qd);
+                    qd_xp = edge_hi ? qd : xhi;
+                    qd_xm = edge_lo ? qd : xlo;
+                } else {
+                    qd_xp = Qc[q + YM + cxp];
+                    qd_xm = Qc[q + YM + cxm];
+                }
+                v2 = pseudo_velocity(u2_m1, sH[q + YM] + h_m1, qd, p1_m1, sC3[q + YM] + c3_m1,
+                                     p1_hi + Qhi[q + YM], p1_lo + Qlo[q + YM], sC1[q + YM] + c1_m1,
+                                     qxp_ + qd_xp, qxm_ + qd_xm, eps);
+                if (zero_v2) v2 = T(0);
+            }
             __builtin_amdgcn_sched_barrier(0);
-            // z-face t between a = plane t-1 and b = plane t; transverse x then y
-            v3 = pseudo_velocity(cur.u3lo, h_m1 + curA.h, p1_m1, p1_c, c1_m1 + c1_c,
-                                 Qb[q + cxp] + qxp_, Qb[q + cxm] + qxm_, c2_m1 + c2_c,
-                                 Qb[q + cyp] + qyp_, Qb[q + cym] + qym_, eps);
+            {
+                // z-face t between a = plane t-1 and b = plane t; transverse x then y
+                T pc_xp, pc_xm;
+                if constexpr (kDpp) {
+                    const T xhi = from_hi(p1_c), xlo = from_lo(p1_c);
+                    pc_xp = edge_hi ? p1_c : xhi;
+                    pc_xm = edge_lo ? p1_c : xlo;
+                } else {
+                    pc_xp = Qb[q + cxp];
+                    pc_xm = Qb[q + cxm];
+                }
+                v3 = pseudo_velocity(cur.u3lo, h_m1 + curA.h, p1_m1, p1_c, c1_m1 + c1_c,
+                                     pc_xp + qxp_, pc_xm + qxm_, c2_m1 + c2_c,
+                                     Qb[q + cyp] + qyp_, Qb[q + cym] + qym_, eps);
+            }
             if (OPEN && (t <= 0 || t >= nz)) v3 = T(0);
             if (NONOS) {
                 // ---- S4 bounds at plane p
-                const T pn_lo = clo ? pn_m1 : pn_m2, pn_hi = chi ? pn_m1 : cur.pn;
-                mx = fmax(fmax(fmax(pmx_m1, fmax(qxm_, qxp_)), fmax(fmax(qym_, qyp_), p1_m1)),
-                          fmax(fmax(pn_lo, pn_hi), fmax(p1_lo, p1_hi)));
-                mn = fmin(fmin(fmin(pmn_m1, fmin(qxm_, qxp_)), fmin(fmin(qym_, qyp_), p1_m1)),
-                          fmin(fmin(pn_lo, pn_hi), fmin(p1_lo, p1_hi)));
-                sFA1[q] = donor(qa, p1_m1, v1);
-                sFA2[q] = donor(qd, p1_m1, v2);
+                // psi^n(t) is the plane above p (at an open top, p itself)
+                const T pn_hi = chi ? pn_m1 : cur.pn;
+                mx = fmax(fmax(fmax(zmx_m1, fmax(qxm_, qxp_)), fmax(fmax(qym_, qyp_), p1_m1)),
+                          fmax(pn_hi, fmax(p1_lo, p1_hi)));
+                mn = fmin(fmin(fmin(zmn_m1, fmin(qxm_, qxp_)), fmin(fmin(qym_, qyp_), p1_m1)),
+                          fmin(pn_hi, fmin(p1_lo, p1_hi)));
+                fa1 = donor(qa, p1_m1, v1);
+                fa2 = donor(qd, p1_m1, v2);
+                if constexpr (!kDpp) sFA1[q] = fa1;
+                sFA2[q] = fa2;
                 fa3_c = donor(p1_m1, p1_c, v3);
             }
         }
         // psi^n of plane t+1: every read of plane t in sP happened before (D)
-        store_ring(nx1);
+        sP[q] = nx1.pn;
+        if (has_ring) sP[p_ring] = rng;
         __syncthreads();  // (F) antidiffusive fluxes visible
 
         L bu_m1 = 1.0, bd_m1 = 1.0;
         if (NONOS) {
             // ---- S5 limiter factors at plane t-1
-            const L x_lo = L(sFA1[q]), x_hi = L(sFA1[q + XP]);
-            const L y_lo = L(sFA2[q]), y_hi = L(sFA2[q + YP]);
+            T fa1_hi;
+            if constexpr (kDpp) fa1_hi = from_hi(fa1);
+            else fa1_hi = sFA1[q + XP];
+            const L x_lo = L(fa1), x_hi = L(fa1_hi);
+            const L y_lo = L(fa2), y_hi = L(sFA2[q + YP]);
             const L z_lo = L(fa3_m1), z_hi = L(fa3_c);
             const L in = ((pos(x_lo) - neg(x_hi)) + (pos(y_lo) - neg(y_hi))) + (pos(z_lo) - neg(z_hi));
             const L ou = ((pos(x_hi) - neg(x_lo)) + (pos(y_hi) - neg(y_lo))) + (pos(z_hi) - neg(z_lo));
@@ -483,22 +597,30 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
             bd_m1 = ((L(p1_m1) - L(mn)) * din) * r;
         }
 
-        T fc3_m1;
+        T fc1_r, fc2_r, fc3_m1;
         {
             // ---- S6 + corrective fluxes at plane r = t-2 (lower faces) and on face t-1;
-            // the fluxes of t-3 in sFC were read before (D)
+            // the y-fluxes of t-3 in sFC2 were read before (D)
             const T *Qr = sQ[s2];
             T vt1 = v1_m2, vt2 = v2_m2, vt3 = v3_m1;
             if (NONOS) {
-                vt1 = limited(v1_m2, sBU[q + XM], sBD[q + XM], bu_m2, bd_m2);
+                L bu_a, bd_a;
+                if constexpr (kDpp) bu_a = from_lo(bu_m2), bd_a = from_lo(bd_m2);
+                else bu_a = sBU[q + XM], bd_a = sBD[q + XM];
+                vt1 = limited(v1_m2, bu_a, bd_a, bu_m2, bd_m2);
                 vt2 = limited(v2_m2, sBU[q + YM], sBD[q + YM], bu_m2, bd_m2);
                 vt3 = limited(v3_m1, bu_m2, bd_m2, bu_m1, bd_m1);
             }
             if (zero_v1) vt1 = T(0);
             if (zero_v2) vt2 = T(0);
             if (OPEN && (t - 1 <= 0 || t - 1 >= nz)) vt3 = T(0);
-            sFC1[q] = donor(Qr[q + XM], p1_m2, vt1);
-            sFC2[q] = donor(Qr[q + YM], p1_m2, vt2);
+            T p2_xm;
+            if constexpr (kDpp) p2_xm = from_lo(p1_m2);
+            else p2_xm = Qr[q + XM];
+            fc1_r = donor(p2_xm, p1_m2, vt1);
+            fc2_r = donor(Qr[q + YM], p1_m2, vt2);
+            if constexpr (!kDpp) sFC1[q] = fc1_r;
+            sFC2[q] = fc2_r;
             fc3_m1 = donor(p1_m2, p1_m1, vt3);
         }
         // sums/h of plane t for the next iteration: the reads of plane t-1
@@ -507,12 +629,12 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         sC2[q] = c2_c;
         sC3[q] = c3_c;
         sH[q] = curA.h;
+        rng = load_ring(ka);  // plane t+2
 
         // ---- hand the planes to the next iteration
-        pn_m2 = pn_m1;
         pn_m1 = cur.pn;
-        pmx_m1 = pmx_c;
-        pmn_m1 = pmn_c;
+        zmx_m1 = zmx_c;
+        zmn_m1 = zmn_c;
         u1_m1 = curA.u1lo;
         u2_m1 = curA.u2lo;
         rh_m3 = rh_m2;
@@ -527,6 +649,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         bd_m2 = bd_m1;
         fc3_m3 = fc3_m2;
         fc3_m2 = fc3_m1;
+        fc1_m3 = fc1_r;
+        if (kHist) fc2_m3 = fc2_r;
         if (kHist) {
             r_p1_m3 = p1_m2;
             r_p1_m2 = p1_m1;
@@ -568,7 +692,8 @@ __global__ __launch_bounds__(RX * RY) void step_kernel(const GridDesc<T> *__rest
         sm.sP[i] = T(0);
         sm.sQ[0][i] = sm.sQ[1][i] = sm.sQ[2][i] = T(0);
         sm.sC1[i] = sm.sC2[i] = sm.sC3[i] = sm.sH[i] = T(0);
-        sm.sFA1[i] = sm.sFA2[i] = sm.sFC1[i] = sm.sFC2[i] = T(0);
+        sm.sFA2[i] = sm.sFC2[i] = T(0);
+        if (i < Smem<T, RX, RY>::PX1) sm.sFA1[i] = sm.sFC1[i] = T(0);
         sm.sBU[i] = sm.sBD[i] = 1.0;
     }
     __syncthreads();
