@@ -81,10 +81,12 @@ template <bool OPEN> __device__ __forceinline__ int face_hi(int i, int n)
 template <typename T> __device__ __forceinline__ T pos(T x) { return fmax(x, T(0)); }
 template <typename T> __device__ __forceinline__ T neg(T x) { return fmin(x, T(0)); }
 
-// donor-cell flux through a face with lower value l, upper value r
+// donor-cell flux through a face with lower value l, upper value r:
+// pos(c) l + neg(c) r, evaluated as c times the upwind value (the same
+// number: one of the two products is an exact zero)
 template <typename T> __device__ __forceinline__ T donor(T l, T r, T c)
 {
-    return pos(c) * l + neg(c) * r;
+    return c * (c > T(0) ? l : r);
 }
 
 // Reciprocal by the hardware estimate (v_rcp_f64 is good to about 2^-24,
@@ -167,12 +169,13 @@ __device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi
     }
 }
 
-// Limited pseudo-velocity; the factors are in limiter precision (double).
+// Limited pseudo-velocity; the factors are in limiter precision (double)
+// and already capped at 1 (min(1, a, b) = min(min(1, a), min(1, b)) exactly).
 template <typename T>
 __device__ __forceinline__ T limited(T v, double bup_a, double bdn_a, double bup_b, double bdn_b)
 {
-    const T cp = T(fmin(1.0, fmin(bdn_a, bup_b)));
-    const T cn = T(fmin(1.0, fmin(bup_a, bdn_b)));
+    const T cp = T(fmin(bdn_a, bup_b));
+    const T cn = T(fmin(bup_a, bdn_b));
     return cp * pos(v) + cn * neg(v);
 }
 
@@ -422,7 +425,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     T r_c1_m1 = T(0), r_c2_m1 = T(0), r_c3_m1 = T(0), r_h_m1 = T(0);
     T v1_m2 = T(0), v2_m2 = T(0), v3_m1 = T(0); // V at plane t-2, V3 at face t-1
     T fa3_m1 = T(0);                            // antidiffusive flux, face t-1
-    L bu_m2 = 1.0, bd_m2 = 1.0;                 // limiter factors, plane t-2
+    L bu_m2 = 1.0, bd_m2 = 1.0;                 // limiter factors (capped at 1), plane t-2
     T fc3_m2 = T(0), fc3_m3 = T(0);             // corrective flux, faces t-2, t-3
     T fc1_m3 = T(0), fc2_m3 = T(0);             // corrective fluxes, lower x/y faces of plane t-3
 
@@ -478,6 +481,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         __syncthreads();  // (D) psi1(t) and the limiter factors of t-2 are visible
 
         T v1, v2, v3, fa1 = T(0), fa2 = T(0), fa3_c = T(0);
+        T pc_xlo = T(0), p2_xm = T(0);
         T mx = T(0), mn = T(0);
         {
             // ---- S3 at plane p = t-1 (lower x- and y-faces) and on face t
@@ -501,6 +505,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
                 const T p1_xhi = from_hi(p1_m1);
                 qxp_ = edge_hi ? p1_m1 : p1_xhi;
                 qxm_ = edge_lo ? p1_m1 : qa;
+                // psi1 of t and t-2 of the lower x-neighbour (reused below)
+                pc_xlo = from_lo(p1_c);
+                p2_xm = from_lo(p1_m2);
             } else {
                 qa = Qc[q + XM];
                 qxp_ = Qc[q + cxp];
@@ -512,7 +519,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
                 if constexpr (kDpp) {
                     h_a = from_lo(h_m1), c2_a = from_lo(c2_m1), c3_a = from_lo(c3_m1);
                     qyp_a = from_lo(qyp_), qym_a = from_lo(qym_);
-                    phi_a = from_lo(p1_hi), plo_a = from_lo(p1_lo);
+                    phi_a = chi ? qa : pc_xlo, plo_a = clo ? qa : p2_xm;
                 } else {
                     h_a = sH[q + XM], c2_a = sC2[q + XM], c3_a = sC3[q + XM];
                     qyp_a = Qc[q + XM + cyp], qym_a = Qc[q + XM + cym];
@@ -546,9 +553,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
                 // z-face t between a = plane t-1 and b = plane t; transverse x then y
                 T pc_xp, pc_xm;
                 if constexpr (kDpp) {
-                    const T xhi = from_hi(p1_c), xlo = from_lo(p1_c);
+                    const T xhi = from_hi(p1_c);
                     pc_xp = edge_hi ? p1_c : xhi;
-                    pc_xm = edge_lo ? p1_c : xlo;
+                    pc_xm = edge_lo ? p1_c : pc_xlo;
                 } else {
                     pc_xp = Qb[q + cxp];
                     pc_xm = Qb[q + cxm];
@@ -593,8 +600,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
             // over the common denominator (IN + eps)(OUT + eps)
             const L din = in + eps_l, dou = ou + eps_l;
             const L r = rcp_nr(din * dou) * L(h_m1);
-            bu_m1 = ((L(mx) - L(p1_m1)) * dou) * r;
-            bd_m1 = ((L(p1_m1) - L(mn)) * din) * r;
+            bu_m1 = fmin(L(1), ((L(mx) - L(p1_m1)) * dou) * r);
+            bd_m1 = fmin(L(1), ((L(p1_m1) - L(mn)) * din) * r);
         }
 
         T fc1_r, fc2_r, fc3_m1;
@@ -614,9 +621,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
             if (zero_v1) vt1 = T(0);
             if (zero_v2) vt2 = T(0);
             if (OPEN && (t - 1 <= 0 || t - 1 >= nz)) vt3 = T(0);
-            T p2_xm;
-            if constexpr (kDpp) p2_xm = from_lo(p1_m2);
-            else p2_xm = Qr[q + XM];
+            if constexpr (!kDpp) p2_xm = Qr[q + XM];
             fc1_r = donor(p2_xm, p1_m2, vt1);
             fc2_r = donor(Qr[q + YM], p1_m2, vt2);
             if constexpr (!kDpp) sFC1[q] = fc1_r;
