@@ -415,9 +415,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     T u1_m1 = T(0), u2_m1 = T(0);               // lower-face Courant, plane t-1
     T rh_m1 = T(1), rh_m2 = T(1), rh_m3 = T(1); // 1/h of planes t-1 .. t-3
     // Own-column psi1 of planes t-1 .. t-3 and the Courant sums and h of plane
-    // t-1 also sit in LDS; FP32 has the registers to keep a copy and save
-    // seven LDS reads per iteration, FP64 reads them back.
-    constexpr bool kHist = sizeof(T) == 4;
+    // t-1 also sit in LDS (for the neighbours); the column keeps its own copy
+    // in registers.
     // x-neighbours by lane exchange (FP64, where LDS bandwidth binds) or
     // through LDS (FP32, where the exchange costs more issue than it saves)
     constexpr bool kDpp = sizeof(T) == 8;
@@ -437,11 +436,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         ka = kb;
         kb = next_plane(kb, t + 3);
         __syncthreads();  // (B) psi^n(t), sums/h of t-1, corrective y-fluxes of t-3 are visible
-        // own-column values of planes t-1 .. t-3 that already sit in LDS
-        const T p1_m1 = kHist ? r_p1_m1 : sQ[s1][q], p1_m2 = kHist ? r_p1_m2 : sQ[s2][q];
-        const T p1_m3 = kHist ? r_p1_m3 : sQ[s0][q];
-        const T c1_m1 = kHist ? r_c1_m1 : sC1[q], c2_m1 = kHist ? r_c2_m1 : sC2[q];
-        const T c3_m1 = kHist ? r_c3_m1 : sC3[q], h_m1 = kHist ? r_h_m1 : sH[q];
+        // own-column values of planes t-1 .. t-3
+        const T p1_m1 = r_p1_m1, p1_m2 = r_p1_m2, p1_m3 = r_p1_m3;
+        const T c1_m1 = r_c1_m1, c2_m1 = r_c2_m1, c3_m1 = r_c3_m1, h_m1 = r_h_m1;
 
         // limiter factors of plane t-2 (computed last iteration) for the
         // neighbours' corrective pass after (F); their previous contents were
@@ -456,7 +453,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
             if constexpr (kDpp) fc1hi = from_hi(fc1_m3);
             else fc1hi = sFC1[q + XP];
             const T fc2hi = sFC2[q + YP];
-            const T fc2lo = kHist ? fc2_m3 : sFC2[q];
+            const T fc2lo = fc2_m3;
             const T res = p1_m3 - (((fc1hi - fc1_m3) + (fc2hi - fc2lo)) + (fc3_m2 - fc3_m3)) * rh_m3;
             if (is_out && t >= z0 + 3 && t <= tend)
                 bstore<T>(plane_rsrc<T>(psi_out, t - 3, pc_cells), b_c, res);
@@ -655,8 +652,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         fc3_m3 = fc3_m2;
         fc3_m2 = fc3_m1;
         fc1_m3 = fc1_r;
-        if (kHist) fc2_m3 = fc2_r;
-        if (kHist) {
+        fc2_m3 = fc2_r;
+        {
             r_p1_m3 = p1_m2;
             r_p1_m2 = p1_m1;
             r_p1_m1 = p1_c;
