@@ -404,8 +404,9 @@ static int engine_step(Engine &e, int32_t nsteps)
             r = build_graph(e);
             if (r != hipSuccess) {
                 e.use_graph = false;  // fall back to plain launches of the same kernel
-                if (e.graph) hipGraphExecDestroy(e.graph);
-                if (e.graph_def) hipGraphDestroy(e.graph_def);
+                // teardown of a failed build: errors here change nothing
+                if (e.graph) (void)hipGraphExecDestroy(e.graph);
+                if (e.graph_def) (void)hipGraphDestroy(e.graph_def);
                 e.graph = nullptr;
                 e.graph_def = nullptr;
                 (void)hipGetLastError();
@@ -573,10 +574,11 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
     return MPDATA_OK;
 }
 
+// Destroy paths report nothing: the objects are gone either way.
 static void engine_release(Engine &e)
 {
-    if (e.graph) hipGraphExecDestroy(e.graph);
-    if (e.graph_def) hipGraphDestroy(e.graph_def);
+    if (e.graph) (void)hipGraphExecDestroy(e.graph);
+    if (e.graph_def) (void)hipGraphDestroy(e.graph_def);
     e.graph = nullptr;
     e.graph_def = nullptr;
 }
@@ -1125,8 +1127,8 @@ void mpdata_pool_destroy(mpdata_pool *p)
     (void)hipStreamSynchronize(p->e.stream);
     engine_release(p->e);
     for (auto &st : p->stage) {
-        if (st.done) hipEventDestroy(st.done);
-        if (st.host) hipHostFree(st.host);
+        if (st.done) (void)hipEventDestroy(st.done);
+        if (st.host) (void)hipHostFree(st.host);
     }
     delete p;
 }
