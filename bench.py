@@ -307,6 +307,11 @@ def main():
     abytes = algorithmic_bytes(fields.shape, word)
     achieved = abytes / (ms_per_step / 1e3) / 1e9
 
+    from paper_1507_01265_amd import _lib
+    tile = args.tile or _lib.mpdata_default_tile(
+        _lib.MPDATA_FP64 if dtag == "f64" else _lib.MPDATA_FP32, int(fields.bc))
+    tx, ty, threads = _lib.mpdata_tile_info(tile)
+
     line = {
         "metric": "MPDATA cell-updates/s per step",
         "value": value,
@@ -322,7 +327,7 @@ def main():
         "data": "synthetic (seeded generator, resident in HBM)",
         "config": {"workload": desc, "nx": nx, "ny": ny, "nz": nz,
                    "bc": "periodic" if fields.bc == 0 else "open", "iord": 2, "nonos": True,
-                   "tile": args.tile},
+                   "tile": tile, "output_tile": f"{tx}x{ty}", "threads_per_workgroup": threads},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "algorithmic_bytes_per_launch": abytes},

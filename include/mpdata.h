@@ -140,6 +140,10 @@ const char *mpdata_last_error(const mpdata_ctx *ctx);
 int mpdata_tile_count(void);
 int mpdata_tile_info(int32_t id, int32_t *tx, int32_t *ty, int32_t *threads);
 
+/* The shape id that params.tile = 0 selects for (dtype, bc), or 0 if dtype
+ * or bc is not one of the enum values. */
+int32_t mpdata_default_tile(int32_t dtype, int32_t bc);
+
 /* Resident workgroups of the step kernel for (dtype, tile, bc, nonos) on the
  * current device: *per_cu per compute unit, *cus compute units. */
 int mpdata_occupancy(int32_t dtype, int32_t tile, int32_t bc, int32_t nonos, int32_t *per_cu,

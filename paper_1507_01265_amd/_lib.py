@@ -54,6 +54,7 @@ _lib = None
 _SIGNATURES = {
     "mpdata_abi_version": ([], ctypes.c_int),
     "mpdata_tile_count": ([], ctypes.c_int),
+    "mpdata_default_tile": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "mpdata_tile_info": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
                          ctypes.c_int),
@@ -154,6 +155,10 @@ def mpdata_abi_version() -> int:
 
 def mpdata_tile_count() -> int:
     return load().mpdata_tile_count()
+
+
+def mpdata_default_tile(dtype: int, bc: int) -> int:
+    return load().mpdata_default_tile(dtype, bc)
 
 
 def mpdata_tile_info(tile_id: int):

@@ -63,7 +63,7 @@ class Batch:
         if plan is not None:
             self.tile, self.nseg = plan[0], cplan.nseg
         else:
-            self.tile = tile if tile else (2 if (dtype == torch.float32 and bc == "open") else 5)
+            self.tile = tile if tile else _lib.mpdata_default_tile(DTYPES[dtype], BC[bc])
             self.nseg, _ = _lib.mpdata_batch_default_plan_size(self.params, self.tile)
 
     @classmethod

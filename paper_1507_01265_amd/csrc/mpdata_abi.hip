@@ -733,6 +733,13 @@ int mpdata_tile_info(int32_t id, int32_t *tx, int32_t *ty, int32_t *threads)
     return MPDATA_OK;
 }
 
+int32_t mpdata_default_tile(int32_t dtype, int32_t bc)
+{
+    if (dtype != MPDATA_FP64 && dtype != MPDATA_FP32) return 0;
+    if (bc != MPDATA_BC_PERIODIC && bc != MPDATA_BC_OPEN) return 0;
+    return default_tile(dtype, bc);
+}
+
 int mpdata_occupancy(int32_t dtype, int32_t tile, int32_t bc, int32_t nonos, int32_t *per_cu,
                      int32_t *cus)
 {

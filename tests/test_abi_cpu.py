@@ -43,6 +43,14 @@ def test_abi_version_and_tiles():
         _lib.mpdata_tile_info(n + 1)
 
 
+def test_default_tile_is_a_valid_shape():
+    n = _lib.mpdata_tile_count()
+    for dtype in (_lib.MPDATA_FP64, _lib.MPDATA_FP32):
+        for bc in (_lib.MPDATA_BC_PERIODIC, _lib.MPDATA_BC_OPEN):
+            assert 1 <= _lib.mpdata_default_tile(dtype, bc) <= n
+    assert _lib.mpdata_default_tile(7, 0) == 0 and _lib.mpdata_default_tile(0, 7) == 0
+
+
 def _params(**kw):
     d = dict(nx=32, ny=32, nz=16, dtype=0, bc=0, iord=2, nonos=1, tile=0, eps=1e-15)
     d.update(kw)
