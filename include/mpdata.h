@@ -245,6 +245,31 @@ const char *mpdata_pool_last_error(const mpdata_pool *pool);   /* NULL: last cre
 void mpdata_batch_destroy(mpdata_batch *b);                 /* NULL-safe */
 const char *mpdata_batch_last_error(const mpdata_batch *b); /* NULL: last create */
 
+/* -------------------------------------- model-based load imbalancing (host)
+ * The paper's functional performance model (section 3) and its partitioning
+ * algorithm (section 4, Algorithm 1) for p identical processors -- here the
+ * XCDs of one GPU, each running a slab of planes of one grid.  speed[k] is
+ * s(k*dx), the speed of one processor on a workload of k granules measured
+ * while all processors run together (k = 0..nspeed-1; speed[0] unused; any
+ * positive unit).  Host-only: no device is touched. */
+
+/* Theorem 1's condition s(x)/x >= s(y)/y for all x < y over the table.
+ * Returns the number of violating pairs (>= 0; 0 = the balanced split is
+ * optimal), the first one in (*x_bad, *y_bad) as workloads (may be NULL),
+ * or MPDATA_EINVAL for a bad table (nspeed < 2, dx < 1, a speed <= 0). */
+int mpdata_fpm_check(const double *speed, int32_t nspeed, int32_t dx, int32_t *x_bad,
+                     int32_t *y_bad);
+
+/* Algorithm 1: workload n (multiple of p*dx), p even.  Starting from the even
+ * share n/p, moves dx at a time from half of the processors to the other
+ * half while the smaller share keeps at least dx, timing each split as
+ * max(x_hi/s(x_hi), x_lo/s(x_lo)), and returns the first split of least
+ * time: *x_lo for the odd-numbered processors, *x_hi for the even-numbered
+ * ones, *t_min the predicted time (x unit / s unit).  The table must cover
+ * every workload the moves reach (2n/p - dx); MPDATA_EINVAL otherwise. */
+int mpdata_fpm_partition(const double *speed, int32_t nspeed, int32_t n, int32_t p, int32_t dx,
+                         int32_t *x_lo, int32_t *x_hi, double *t_min);
+
 /* Version of this ABI (MPDATA_ABI_VERSION). */
 int mpdata_abi_version(void);
 

@@ -55,6 +55,13 @@ _SIGNATURES = {
     "mpdata_abi_version": ([], ctypes.c_int),
     "mpdata_tile_count": ([], ctypes.c_int),
     "mpdata_default_tile": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
+    "mpdata_fpm_check": ([ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int32,
+                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+                         ctypes.c_int),
+    "mpdata_fpm_partition": ([ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
+                             ctypes.c_int),
     "mpdata_tile_info": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
                          ctypes.c_int),
@@ -155,6 +162,32 @@ def mpdata_abi_version() -> int:
 
 def mpdata_tile_count() -> int:
     return load().mpdata_tile_count()
+
+
+def _speed_table(speed):
+    arr = (ctypes.c_double * len(speed))(*[float(v) for v in speed])
+    return arr, len(speed)
+
+
+def mpdata_fpm_check(speed, dx: int = 1):
+    """Theorem 1's condition over speed[k] = s(k*dx): (violations, first pair or None)."""
+    arr, n = _speed_table(speed)
+    xb, yb = ctypes.c_int32(), ctypes.c_int32()
+    r = load().mpdata_fpm_check(arr, n, dx, ctypes.byref(xb), ctypes.byref(yb))
+    if r < 0:
+        raise MpdataError(r, "mpdata_fpm_check: invalid speed table")
+    return r, ((xb.value, yb.value) if r else None)
+
+
+def mpdata_fpm_partition(speed, n: int, p: int, dx: int = 1):
+    """Algorithm 1 over speed[k] = s(k*dx): (x_lo, x_hi, t_min)."""
+    arr, ns = _speed_table(speed)
+    lo, hi, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    r = load().mpdata_fpm_partition(arr, ns, n, p, dx, ctypes.byref(lo), ctypes.byref(hi),
+                                    ctypes.byref(t))
+    if r < 0:
+        raise MpdataError(r, "mpdata_fpm_partition: invalid arguments")
+    return lo.value, hi.value, t.value
 
 
 def mpdata_default_tile(dtype: int, bc: int) -> int:

@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -730,6 +731,56 @@ int mpdata_tile_info(int32_t id, int32_t *tx, int32_t *ty, int32_t *threads)
     if (tx) *tx = s[id - 1].rx - 4;
     if (ty) *ty = s[id - 1].ry - 4;
     if (threads) *threads = s[id - 1].rx * s[id - 1].ry;
+    return MPDATA_OK;
+}
+
+int mpdata_fpm_check(const double *speed, int32_t nspeed, int32_t dx, int32_t *x_bad,
+                     int32_t *y_bad)
+{
+    if (!speed || nspeed < 2 || dx < 1) return MPDATA_EINVAL;
+    for (int32_t k = 1; k < nspeed; ++k)
+        if (!(speed[k] > 0.0) || !std::isfinite(speed[k])) return MPDATA_EINVAL;
+    // s(x)/x is compared for every pair x < y; the table is small
+    int count = 0;
+    for (int32_t a = 1; a < nspeed; ++a)
+        for (int32_t b = a + 1; b < nspeed; ++b)
+            if (speed[a] / (double)(a * dx) < speed[b] / (double)(b * dx)) {
+                if (count == 0) {
+                    if (x_bad) *x_bad = a * dx;
+                    if (y_bad) *y_bad = b * dx;
+                }
+                ++count;
+            }
+    return count;
+}
+
+int mpdata_fpm_partition(const double *speed, int32_t nspeed, int32_t n, int32_t p, int32_t dx,
+                         int32_t *x_lo, int32_t *x_hi, double *t_min)
+{
+    if (!speed || !x_lo || !x_hi || !t_min || dx < 1 || p < 2 || p % 2 || n < 1 || n % p ||
+        (n / p) % dx)
+        return MPDATA_EINVAL;
+    const int32_t share = n / p;
+    // the moves reach x_hi = 2 share - dx: granule index 2 share/dx - 1
+    if (nspeed < 2 * (share / dx)) return MPDATA_EINVAL;
+    for (int32_t k = 1; k < 2 * (share / dx); ++k)
+        if (!(speed[k] > 0.0) || !std::isfinite(speed[k])) return MPDATA_EINVAL;
+    auto time_of = [&](int32_t x) { return (double)x / speed[x / dx]; };
+    int32_t lo = share, hi = share, best_lo = share, best_hi = share;
+    double best = time_of(share);
+    while (lo - dx >= dx) {
+        hi += dx;
+        lo -= dx;
+        const double t = std::max(time_of(hi), time_of(lo));
+        if (t < best) {
+            best = t;
+            best_lo = lo;
+            best_hi = hi;
+        }
+    }
+    *x_lo = best_lo;
+    *x_hi = best_hi;
+    *t_min = best;
     return MPDATA_OK;
 }
 
