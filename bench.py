@@ -39,6 +39,10 @@ WORKLOADS = {
                      "96 uneven periodic grids (nx, ny log-uniform in [32, 384], nz in [16, 64]), "
                      "FP32 + FP64 limiter, constant Courant per grid, one persistent launch per "
                      "step"),
+    "teams-fp64": ("teams", "f64",
+                   "rotation 512x256x64 periodic FP64 split into z-slabs over the 8 XCDs "
+                   "(the paper's teams): speed functions measured with all teams running, "
+                   "Theorem 1 check, Algorithm 1 split vs the even split"),
     "served": ("served", "mixed",
                "Poisson arrivals 200/s for 60 s, dims log-uniform [32,256]^2 x [16,64], steps "
                "uniform [10,200], 70% FP32 / 30% FP64, solid-body rotation, 200 GB HBM budget, "
@@ -241,6 +245,33 @@ def bench_served(args):
             "single_grid_sample": len(sample)}
 
 
+def bench_teams(args):
+    """The paper's load-imbalancing procedure with the XCDs as teams, on the
+    512x256x64 FP64 rotation grid: value = cell-updates/s of the split
+    Algorithm 1 picks (the even split when Theorem 1's condition holds)."""
+    import numpy as np
+    import torch
+    from paper_1507_01265_amd import inputs, teams
+
+    full = inputs.rotation(shape=(8 * 15, 256, 512))  # one field, sliced per plane count
+
+    def make(nz):
+        f = full
+        return inputs.Fields(f.psi[:nz], f.u1[:nz], f.u2[:nz], f.u3[:nz + 1], f.h[:nz], f.bc)
+
+    print("# teams: speed functions, Algorithm 1, splits", file=sys.stderr, flush=True)
+    ex = teams.experiment(make, 64, torch.float64, args.tile or 5, steps=args.steps)
+    chosen = [r for r in ex["splits"] if r["dm"] == ex["algorithm1"]["dm"]][0]
+    even = [r for r in ex["splits"] if r["dm"] == 0][0]
+    return {"metric": "MPDATA cell-updates/s per step", "value": ex["cells"] / (chosen["measured_ms"] / 1e3),
+            "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 2,
+            "ms_per_step": chosen["measured_ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator, resident in HBM)",
+            "config": {"workload": WORKLOADS["teams-fp64"][2], "teams": teams.XCDS, "tile": args.tile or 5},
+            "even_split_ms": even["measured_ms"], "speedup_vs_even": even["measured_ms"] / chosen["measured_ms"],
+            "teams": ex}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +310,10 @@ def main():
                 "config": {"workload": desc, "cells": r["cells"]}}
         line.update(r["extra"])
         print(json.dumps(line), flush=True)
+        return
+    if kind == "teams":
+        r = bench_teams(args)
+        print(json.dumps(r), flush=True)
         return
     if kind == "served":
         r = bench_served(args)

@@ -391,9 +391,6 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
     };
 
     const int t0 = z0 - 2, tend = z1 + 2;
-    // the march runs a multiple of three iterations; iterations past tend
-    // only reload valid planes and store nothing
-    const int tstop = t0 + ((tend - t0 + 1 + 2) / 3) * 3 - 1;
     PlaneA<T> curA, nxA;
     PlaneB<T> cur, nx1, nx2;
     int ka = plane_of(t0 + 1);                     // plane of t+1 (load_a)
@@ -667,7 +664,21 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
         nx1 = nx2;
     };
 
-    for (int t = t0; t <= tstop; t += 3) {
+    // Unrolled by three so the psi1 planes sit in fixed slots (slot of plane
+    // t = (t - t0 + shift) mod 3); the iteration count modulo three is run
+    // first, in the last slots, so that no iteration is wasted.
+    int t = t0;
+    switch ((tend - t0 + 1) % 3) {
+    case 2:
+        iter(t++, std::integral_constant<int, 1>{});
+        [[fallthrough]];
+    case 1:
+        iter(t++, std::integral_constant<int, 2>{});
+        break;
+    default:
+        break;
+    }
+    for (; t <= tend; t += 3) {
         iter(t, std::integral_constant<int, 0>{});
         iter(t + 1, std::integral_constant<int, 1>{});
         iter(t + 2, std::integral_constant<int, 2>{});
