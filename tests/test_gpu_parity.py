@@ -249,6 +249,26 @@ def test_full_size_rotation_fp64(orc):
 
 
 @pytest.mark.slow
+def test_full_size_rotation_fp64_100_steps(orc):
+    """512x256x64 rotation, the benchmark's 100 steps: the scheme's rounding
+    differences must not grow past the FP64 bound over a whole run."""
+    f = inputs.rotation()
+    want = oracle_run(orc, f, 100)
+    got = gpu_run(f, 100)
+    assert rel_linf(got, want) <= 1e-12
+    assert got.min() >= -1e-15
+
+
+@pytest.mark.slow
+def test_full_size_streamfunction_fp64(orc):
+    """1024x512x64 open domain in FP64 (the open FP64 kernel), 2 steps."""
+    f = inputs.streamfunction()
+    want = oracle_run(orc, f, 2)
+    got = gpu_run(f, 2)
+    assert rel_linf(got, want) <= 1e-12
+
+
+@pytest.mark.slow
 def test_full_size_streamfunction_fp32(orc):
     """1024x512x64 open domain, FP32 + FP64 limiter, 1 step at full size."""
     f = inputs.streamfunction().astype(np.float32)
