@@ -35,6 +35,7 @@ class _Params(ctypes.Structure):
         ("bc", ctypes.c_int),
         ("iord", ctypes.c_int),
         ("nonos", ctypes.c_int),
+        ("vsign", ctypes.c_int),
         ("eps", ctypes.c_double),
     ]
 
@@ -91,9 +92,9 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _params(shape, bc, iord, nonos, eps):
+def _params(shape, bc, iord, nonos, eps, vsign=False):
     nz, ny, nx = shape
-    return _Params(nx, ny, nz, int(bc), int(iord), int(bool(nonos)), float(eps))
+    return _Params(nx, ny, nz, int(bc), int(iord), int(bool(nonos)), int(bool(vsign)), float(eps))
 
 
 def _inputs(psi, u1, u2, u3, h):
@@ -107,10 +108,11 @@ def _inputs(psi, u1, u2, u3, h):
 
 
 def step(psi, u1, u2, u3, h, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15,
-         stages=False):
-    """One step; returns psi at n+1 (and a dict of stage arrays if asked)."""
+         stages=False, vsign=False):
+    """One step; returns psi at n+1 (and a dict of stage arrays if asked).
+    vsign: the variable-sign option (|psi1| in the pseudo-velocity ratios)."""
     psi, u1, u2, u3, h = _inputs(psi, u1, u2, u3, h)
-    p = _params(psi.shape, bc, iord, nonos, eps)
+    p = _params(psi.shape, bc, iord, nonos, eps, vsign)
     out = np.empty_like(psi)
     st = None
     arrays = {}
@@ -129,11 +131,12 @@ def step(psi, u1, u2, u3, h, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15,
     return (out, arrays) if stages else out
 
 
-def run(psi, u1, u2, u3, h, nsteps, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15):
+def run(psi, u1, u2, u3, h, nsteps, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15,
+        vsign=False):
     """nsteps steps; returns a new array."""
     psi, u1, u2, u3, h = _inputs(psi, u1, u2, u3, h)
     psi = psi.copy()
-    p = _params(psi.shape, bc, iord, nonos, eps)
+    p = _params(psi.shape, bc, iord, nonos, eps, vsign)
     rc = _load().orc_run(ctypes.byref(p), _ptr(psi), _ptr(u1), _ptr(u2), _ptr(u3),
                          _ptr(h), int(nsteps))
     if rc:

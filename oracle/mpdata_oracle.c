@@ -41,6 +41,11 @@
  *   - sums of three axis contributions are taken x, then y, then z;
  *     four-term averages are taken as (a+b)+(c+d).
  *
+ * Option vsign (fields of variable sign, from the MPDATA literature the
+ * paper cites -- Smolarkiewicz & Margolin 1998): the ratios A and B of S3
+ * take |psi1| in place of psi1, so their denominators cannot vanish where
+ * the field changes sign; every other stage is unchanged.
+ *
  * Layout: cell arrays are [k][j][i] with i fastest, nx*ny*nz doubles.
  * Face arrays hold n+1 faces along their own axis: u1[k][j][i'] with
  * i' = 0..nx (face i' lies between cells i'-1 and i'), u2[k][j'][i],
@@ -359,6 +364,7 @@ int orc_check(const orc_params *p)
     if (p->bc != ORC_BC_PERIODIC && p->bc != ORC_BC_OPEN) return -1;
     if (p->iord != 1 && p->iord != 2) return -1;
     if (p->nonos != 0 && p->nonos != 1) return -1;
+    if (p->vsign != 0 && p->vsign != 1) return -1;
     if (!(p->eps > 0.0)) return -1;
     return 0;
 }
@@ -392,7 +398,19 @@ int orc_step(const orc_params *p, const double *psi, const double *u1,
         free(p1); free(v1); free(v2); free(v3); free(mx); free(mn); free(bu); free(bd);
         return -2;
     }
-    pseudo_velocities(&g, p1, u1, u2, u3, h, p->eps, v1, v2, v3);   /* S3 */
+    if (p->vsign) {
+        /* S3 on |psi1| (option vsign); the limiter and S7 keep psi1 */
+        double *a1 = malloc(sizeof(double) * n);
+        if (!a1) {
+            free(p1); free(v1); free(v2); free(v3); free(mx); free(mn); free(bu); free(bd);
+            return -2;
+        }
+        for (long c = 0; c < n; ++c) a1[c] = fabs(p1[c]);
+        pseudo_velocities(&g, a1, u1, u2, u3, h, p->eps, v1, v2, v3);
+        free(a1);
+    } else {
+        pseudo_velocities(&g, p1, u1, u2, u3, h, p->eps, v1, v2, v3);   /* S3 */
+    }
     if (st && st->v1) memcpy(st->v1, v1, sizeof(double) * n1);
     if (st && st->v2) memcpy(st->v2, v2, sizeof(double) * n2);
     if (st && st->v3) memcpy(st->v3, v3, sizeof(double) * n3);

@@ -18,6 +18,7 @@ typedef struct {
     int bc;         /* ORC_BC_PERIODIC or ORC_BC_OPEN */
     int iord;       /* 1: donor cell only; 2: one corrective pass */
     int nonos;      /* 1: non-oscillatory limiter on */
+    int vsign;      /* 1: fields of variable sign -- |psi1| in the ratios A, B */
     double eps;     /* regulariser of ratio denominators */
 } orc_params;
 

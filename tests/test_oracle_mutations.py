@@ -37,6 +37,10 @@ MUTANTS = {
     "inflow_sign": ("double in = ((pos(x_lo) - neg(x_hi))", "double in = ((pos(x_lo) + neg(x_hi))"),
     "beta_without_h": ("bup[c] = (mx[c] - pc) * h[c] / (in + eps);", "bup[c] = (mx[c] - pc) / (in + eps);"),
     "mass_drops_errors": ("c = c + (perr + serr);", "c = c + serr;"),
+    "vsign_ignored": ("for (long c = 0; c < n; ++c) a1[c] = fabs(p1[c]);",
+                      "for (long c = 0; c < n; ++c) a1[c] = p1[c];"),
+    "vsign_in_corrective_pass": ("donor_cell_pass(&g, p1, v1, v2, v3, h, out);                         /* S7 */",
+                                 "for (long c = 0; c < n; ++c) p1[c] = fabs(p1[c]);\n    donor_cell_pass(&g, p1, v1, v2, v3, h, out);"),
 }
 
 
@@ -55,6 +59,9 @@ def _checks():
     out["mass_exact"] = lambda: pins.test_mass_sum_is_exact_to_rounding(oracle)
     out["mass_periodic"] = lambda: pins.test_mass_is_conserved_periodic(oracle)
     out["hand_limiter_variable_h"] = _limiter_variable_h
+    out["vsign_positive"] = lambda: pins.test_vsign_is_the_default_scheme_on_positive_fields(oracle)
+    out["vsign_odd"] = lambda: pins.test_vsign_odd_symmetry_bitwise(oracle)
+    out["vsign_wave"] = lambda: pins.test_vsign_advects_a_sign_changing_wave(oracle)
     return out
 
 
