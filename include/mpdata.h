@@ -62,9 +62,13 @@ enum {
 };
 
 enum { MPDATA_FP64 = 0, MPDATA_FP32 = 1 };
-/* flags: launch every step on its own instead of replaying a captured
- * graph of step launches */
-enum { MPDATA_FLAG_NO_GRAPH = 1 };
+/* flags: NO_GRAPH -- launch every step on its own instead of replaying a
+ * captured graph of step launches.  VSIGN -- fields of variable sign: the
+ * ratios of the antidiffusive pseudo-velocity take |psi1| in place of psi1
+ * (the variable-sign option of the MPDATA literature the paper cites,
+ * Smolarkiewicz & Margolin 1998); built for the default launch shapes
+ * (tile 0, 2 or 5). */
+enum { MPDATA_FLAG_NO_GRAPH = 1, MPDATA_FLAG_VSIGN = 2 };
 enum { MPDATA_BC_PERIODIC = 0, MPDATA_BC_OPEN = 1 }; /* OPEN = zero gradient */
 
 typedef struct {

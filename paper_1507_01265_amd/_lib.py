@@ -25,6 +25,7 @@ MPDATA_FP32 = 1
 MPDATA_BC_PERIODIC = 0
 MPDATA_BC_OPEN = 1
 MPDATA_FLAG_NO_GRAPH = 1
+MPDATA_FLAG_VSIGN = 2
 
 ERRORS = {MPDATA_EINVAL: "EINVAL", MPDATA_ENOMEM: "ENOMEM", MPDATA_EDEVICE: "EDEVICE",
           MPDATA_ENOTSUP: "ENOTSUP", MPDATA_ENONFINITE: "ENONFINITE"}

@@ -75,11 +75,14 @@ const char *check_params(const mpdata_params *p)
     if (p->nonos != 0 && p->nonos != 1) return "nonos must be 0 or 1";
     if (p->nonos && p->iord != 2) return "nonos needs iord 2";
     if (!(p->eps > 0.0) || !isfinite(p->eps)) return "eps must be finite and > 0";
-    if (p->flags & ~MPDATA_FLAG_NO_GRAPH) return "unknown flag bits";
+    if (p->flags & ~(MPDATA_FLAG_NO_GRAPH | MPDATA_FLAG_VSIGN)) return "unknown flag bits";
     if (p->reserved != 0) return "reserved must be 0";
     int count = 0;
     mpd::tile_shapes(&count);
     if (p->tile < 0 || p->tile > count) return "tile id out of range";
+    if ((p->flags & MPDATA_FLAG_VSIGN) && p->tile != 0 &&
+        (shape_of(p->tile).rx != 32 || (shape_of(p->tile).ry != 24 && shape_of(p->tile).ry != 32)))
+        return "the variable-sign option runs on the 32x24 and 32x32 launch shapes (tile 0, 2 or 5)";
     return nullptr;
 }
 
@@ -289,10 +292,18 @@ int device_cus()
     return cus;
 }
 
-int wg_per_cu(int dtype, int tile, bool open, bool nonos)
+// Kernel variant bits of a parameter set.
+int variant_of(const mpdata_params &p)
 {
-    const void *k = dtype == MPDATA_FP32 ? mpd::step_kernel_ptr<float>(tile, open, nonos)
-                                         : mpd::step_kernel_ptr<double>(tile, open, nonos);
+    return (p.bc == MPDATA_BC_OPEN ? mpd::kVariantOpen : 0) | (p.nonos ? mpd::kVariantNonos : 0) |
+           ((p.flags & MPDATA_FLAG_VSIGN) ? mpd::kVariantVsign : 0);
+}
+
+int wg_per_cu(int dtype, int tile, int variant)
+{
+    const void *k = dtype == MPDATA_FP32 ? mpd::step_kernel_ptr<float>(tile, variant)
+                                         : mpd::step_kernel_ptr<double>(tile, variant);
+    if (!k) return 0;
     int per = 0;
     const mpd::TileShape &s = shape_of(tile);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, s.rx * s.ry, 0) != hipSuccess)
@@ -318,6 +329,7 @@ void default_plan_bounds(const std::vector<mpdata_params> &grids, int tile, int 
 struct Engine {
     int dtype, tile, nwg, nseg, ngrids, iord;
     bool open, nonos, use_graph;
+    int variant;  // kernel variant bits (open, nonos, variable sign)
     double eps;
     hipStream_t stream;
     char *ws;
@@ -356,10 +368,10 @@ static hipError_t launch_one(Engine &e, int flip, long long *ticks)
     const int *wg = (const int *)(e.ws + e.lay.wg);
     if (e.dtype == MPDATA_FP32)
         return mpd::launch_persistent<float>((const mpd::GridDesc<float> *)(e.ws + e.lay.grids),
-                                             segs, wg, e.nwg, e.tile, e.open, e.nonos, flip,
+                                             segs, wg, e.nwg, e.tile, e.variant, flip,
                                              e.eps, ticks, e.stream);
     return mpd::launch_persistent<double>((const mpd::GridDesc<double> *)(e.ws + e.lay.grids),
-                                          segs, wg, e.nwg, e.tile, e.open, e.nonos, flip, e.eps,
+                                          segs, wg, e.nwg, e.tile, e.variant, flip, e.eps,
                                           ticks, e.stream);
 }
 
@@ -380,8 +392,8 @@ static hipError_t build_graph(Engine &e)
         void *args[] = {(void *)&gridp, (void *)&segp, (void *)&wgp, (void *)&flips[s],
                         (void *)&e.eps, (void *)&no_ticks};
         hipKernelNodeParams kp{};
-        kp.func = (void *)(e.dtype == MPDATA_FP32 ? mpd::step_kernel_ptr<float>(e.tile, e.open, e.nonos)
-                                                  : mpd::step_kernel_ptr<double>(e.tile, e.open, e.nonos));
+        kp.func = (void *)(e.dtype == MPDATA_FP32 ? mpd::step_kernel_ptr<float>(e.tile, e.variant)
+                                                  : mpd::step_kernel_ptr<double>(e.tile, e.variant));
         kp.gridDim = dim3(e.nwg);
         kp.blockDim = dim3(sh.rx * sh.ry);
         kp.sharedMemBytes = 0;
@@ -472,9 +484,10 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
             return fail_to(errbuf, MPDATA_EINVAL, "grid %d: arrays must be 16-byte aligned", i);
         const mpdata_params &a = params[0], &b = params[i];
         if (a.dtype != b.dtype || a.bc != b.bc || a.iord != b.iord || a.nonos != b.nonos ||
-            a.eps != b.eps || a.tile != b.tile)
+            a.eps != b.eps || a.tile != b.tile ||
+            (a.flags & MPDATA_FLAG_VSIGN) != (b.flags & MPDATA_FLAG_VSIGN))
             return fail_to(errbuf, MPDATA_ENOTSUP,
-                           "grid %d: a batch shares dtype, bc, iord, nonos, eps and tile", i);
+                           "grid %d: a batch shares dtype, bc, iord, nonos, eps, tile and flags", i);
     }
     if (batch && params[0].iord != 2)
         return fail_to(errbuf, MPDATA_ENOTSUP, "batches run the full step (iord 2)");
@@ -487,6 +500,7 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
     e.iord = params[0].iord;
     e.open = params[0].bc == MPDATA_BC_OPEN;
     e.nonos = params[0].nonos != 0;
+    e.variant = variant_of(params[0]);
     e.eps = params[0].eps;
     e.use_graph = !(params[0].flags & MPDATA_FLAG_NO_GRAPH);
     e.stream = (hipStream_t)stream;
@@ -501,6 +515,9 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
             !plan->seg || !plan->wg_begin || plan->reserved != 0)
             return fail_to(errbuf, MPDATA_EINVAL, "invalid plan header");
         e.tile = plan->tile;
+        if (!(e.dtype == MPDATA_FP32 ? mpd::step_kernel_ptr<float>(e.tile, e.variant)
+                                     : mpd::step_kernel_ptr<double>(e.tile, e.variant)))
+            return fail_to(errbuf, MPDATA_ENOTSUP, "no step kernel for this launch shape and variant");
         segs.resize(plan->nseg);
         for (int s = 0; s < plan->nseg; ++s) {
             const int32_t *v = plan->seg + 5 * (size_t)s;
@@ -509,7 +526,7 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
         wg.assign(plan->wg_begin, plan->wg_begin + plan->nwg + 1);
     } else {
         e.tile = tile_of(&params[0]);
-        const int per = wg_per_cu(e.dtype, e.tile, e.open, e.nonos);
+        const int per = wg_per_cu(e.dtype, e.tile, e.variant);
         const int cus = device_cus();
         if (per < 1 || cus < 1) return fail_to(errbuf, MPDATA_EDEVICE, "occupancy query failed");
         default_plan(e.params, e.tile, per * cus, segs, wg);
@@ -797,7 +814,8 @@ int mpdata_occupancy(int32_t dtype, int32_t tile, int32_t bc, int32_t nonos, int
     if (dtype != MPDATA_FP64 && dtype != MPDATA_FP32) return MPDATA_EINVAL;
     if (tile == 0) tile = default_tile(dtype, bc);
     if (tile < 1 || tile > mpdata_tile_count()) return MPDATA_EINVAL;
-    const int per = wg_per_cu(dtype, tile, bc == MPDATA_BC_OPEN, nonos != 0);
+    const int per = wg_per_cu(dtype, tile, (bc == MPDATA_BC_OPEN ? mpd::kVariantOpen : 0) |
+                                               (nonos ? mpd::kVariantNonos : 0));
     const int c = device_cus();
     if (per < 1 || c < 1) return MPDATA_EDEVICE;
     if (per_cu) *per_cu = per;
@@ -919,7 +937,7 @@ int mpdata_batch_default_plan_size(int32_t n, const mpdata_params *params, int32
         if (check_params(&params[i])) return MPDATA_EINVAL;
     if (tile == 0) tile = tile_of(&params[0]);
     if (tile < 1 || tile > mpdata_tile_count()) return MPDATA_EINVAL;
-    const int per = wg_per_cu(params[0].dtype, tile, params[0].bc == MPDATA_BC_OPEN, params[0].nonos != 0);
+    const int per = wg_per_cu(params[0].dtype, tile, variant_of(params[0]));
     const int cus = device_cus();
     if (per < 1 || cus < 1) return MPDATA_EDEVICE;
     std::vector<mpdata_params> v(params, params + n);
@@ -1036,6 +1054,7 @@ int mpdata_pool_create(const mpdata_params *shared, int32_t max_grids, int32_t m
     e.iord = 2;
     e.open = sp.bc == MPDATA_BC_OPEN;
     e.nonos = sp.nonos != 0;
+    e.variant = variant_of(sp);
     e.eps = sp.eps;
     e.use_graph = !(sp.flags & MPDATA_FLAG_NO_GRAPH);
     e.stream = (hipStream_t)stream;
@@ -1045,7 +1064,7 @@ int mpdata_pool_create(const mpdata_params *shared, int32_t max_grids, int32_t m
     e.nseg = 0;
     e.err[0] = 0;
     e.params.assign(1, sp);
-    const int per = wg_per_cu(e.dtype, e.tile, e.open, e.nonos);
+    const int per = wg_per_cu(e.dtype, e.tile, e.variant);
     const int cus = device_cus();
     if (per < 1 || cus < 1) {
         delete p;

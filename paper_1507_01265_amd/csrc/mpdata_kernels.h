@@ -27,13 +27,17 @@ struct TileShape {
 
 const TileShape *tile_shapes(int *count);
 
-// The persistent fused step kernel for (T, tile id, open, nonos), as a
-// function pointer (for graph nodes and occupancy queries).
-template <typename T> const void *step_kernel_ptr(int tile, bool open, bool nonos);
+// Kernel variants: open boundaries, limiter on, variable-sign option.
+enum { kVariantOpen = 1, kVariantNonos = 2, kVariantVsign = 4 };
+
+// The persistent fused step kernel for (T, tile id, variant), as a function
+// pointer (for graph nodes and occupancy queries); nullptr if that variant is
+// not built for that shape.
+template <typename T> const void *step_kernel_ptr(int tile, int variant);
 
 template <typename T>
 hipError_t launch_persistent(const GridDesc<T> *grids, const Segment *segs, const int *wg_begin,
-                             int nwg, int tile, bool open, bool nonos, int flip, double eps,
+                             int nwg, int tile, int variant, int flip, double eps,
                              long long *seg_ticks, hipStream_t s);
 
 // Donor-cell pass only (iord 1), one grid: psi[flip] -> psi[1 - flip].

@@ -276,7 +276,7 @@ template <typename T, int RX, int RY> struct Smem {
 
 // One workgroup advances the output tile (tx, ty) of grid g through planes
 // [z0, z1): psi[flip] -> psi[1 - flip].
-template <typename T, int RX, int RY, bool OPEN, bool NONOS>
+template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN>
 __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, int ty, int z0,
                                       int z1, double eps_d, Smem<T, RX, RY> &sm)
 {
@@ -491,6 +491,11 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
             // y-neighbours from LDS; x-neighbours from the adjacent lanes
             // (FP64) or from LDS (FP32); at an open x-boundary the cell
             // beyond is the cell itself
+            // ratio operands: |psi1| with the variable-sign option
+            auto av = [](T x) -> T {
+                if constexpr (VSIGN) return fabs(x);
+                else return x;
+            };
             const T qd = Qc[q + YM];  // cell a of the lower y-face
             const T qyp_ = Qc[q + cyp], qym_ = Qc[q + cym];
             T qa, qxp_, qxm_;         // qa: cell a of the lower x-face
@@ -519,8 +524,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
                     qyp_a = Qc[q + XM + cyp], qym_a = Qc[q + XM + cym];
                     phi_a = Qhi[q + XM], plo_a = Qlo[q + XM];
                 }
-                v1 = pseudo_velocity(u1_m1, h_a + h_m1, qa, p1_m1, c2_a + c2_m1, qyp_ + qyp_a,
-                                     qym_ + qym_a, c3_a + c3_m1, p1_hi + phi_a, p1_lo + plo_a, eps);
+                v1 = pseudo_velocity(u1_m1, h_a + h_m1, av(qa), av(p1_m1), c2_a + c2_m1,
+                                     av(qyp_) + av(qyp_a), av(qym_) + av(qym_a), c3_a + c3_m1,
+                                     av(p1_hi) + av(phi_a), av(p1_lo) + av(plo_a), eps);
                 if (zero_v1) v1 = T(0);
             }
             // the three faces are scheduled one after another: each face's
@@ -537,9 +543,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
                     qd_xp = Qc[q + YM + cxp];
                     qd_xm = Qc[q + YM + cxm];
                 }
-                v2 = pseudo_velocity(u2_m1, sH[q + YM] + h_m1, qd, p1_m1, sC3[q + YM] + c3_m1,
-                                     p1_hi + Qhi[q + YM], p1_lo + Qlo[q + YM], sC1[q + YM] + c1_m1,
-                                     qxp_ + qd_xp, qxm_ + qd_xm, eps);
+                v2 = pseudo_velocity(u2_m1, sH[q + YM] + h_m1, av(qd), av(p1_m1),
+                                     sC3[q + YM] + c3_m1, av(p1_hi) + av(Qhi[q + YM]),
+                                     av(p1_lo) + av(Qlo[q + YM]), sC1[q + YM] + c1_m1,
+                                     av(qxp_) + av(qd_xp), av(qxm_) + av(qd_xm), eps);
                 if (zero_v2) v2 = T(0);
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -554,9 +561,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
                     pc_xp = Qb[q + cxp];
                     pc_xm = Qb[q + cxm];
                 }
-                v3 = pseudo_velocity(cur.u3lo, h_m1 + curA.h, p1_m1, p1_c, c1_m1 + c1_c,
-                                     pc_xp + qxp_, pc_xm + qxm_, c2_m1 + c2_c,
-                                     Qb[q + cyp] + qyp_, Qb[q + cym] + qym_, eps);
+                v3 = pseudo_velocity(cur.u3lo, h_m1 + curA.h, av(p1_m1), av(p1_c), c1_m1 + c1_c,
+                                     av(pc_xp) + av(qxp_), av(pc_xm) + av(qxm_), c2_m1 + c2_c,
+                                     av(Qb[q + cyp]) + av(qyp_), av(Qb[q + cym]) + av(qym_), eps);
             }
             if (OPEN && (t <= 0 || t >= nz)) v3 = T(0);
             if (NONOS) {
@@ -691,7 +698,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, in
 // advances each one time step.  With seg_ticks non-null the wall-clock
 // duration of every segment is recorded (the per-block speeds a plan tuner
 // measures while all workgroups run together).
-template <typename T, int RX, int RY, bool OPEN, bool NONOS>
+template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN>
 __global__ __launch_bounds__(RX * RY) void step_kernel(const GridDesc<T> *__restrict__ grids,
                                                       const Segment *__restrict__ segs,
                                                       const int *__restrict__ wg_begin, int flip,
@@ -714,7 +721,7 @@ __global__ __launch_bounds__(RX * RY) void step_kernel(const GridDesc<T> *__rest
     for (int s = b; s < e; ++s) {
         const Segment sg = segs[s];
         const long long t_start = seg_ticks ? (long long)wall_clock64() : 0;
-        march<T, RX, RY, OPEN, NONOS>(grids[sg.grid], flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+        march<T, RX, RY, OPEN, NONOS, VSIGN>(grids[sg.grid], flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
         __syncthreads();
         // optional per-segment duration (workgroup-uniform; one lane stores)
         if (seg_ticks && threadIdx.x == 0) seg_ticks[s] = (long long)wall_clock64() - t_start;
@@ -757,36 +764,48 @@ const TileShape *tile_shapes(int *count)
     return shapes;
 }
 
-template <typename T, int RX, int RY> static const void *pick(bool open, bool nonos)
+template <typename T, int RX, int RY, bool VSIGN> static const void *pick4(bool open, bool nonos)
 {
     if (open)
-        return nonos ? (const void *)step_kernel<T, RX, RY, true, true>
-                     : (const void *)step_kernel<T, RX, RY, true, false>;
-    return nonos ? (const void *)step_kernel<T, RX, RY, false, true>
-                 : (const void *)step_kernel<T, RX, RY, false, false>;
+        return nonos ? (const void *)step_kernel<T, RX, RY, true, true, VSIGN>
+                     : (const void *)step_kernel<T, RX, RY, true, false, VSIGN>;
+    return nonos ? (const void *)step_kernel<T, RX, RY, false, true, VSIGN>
+                 : (const void *)step_kernel<T, RX, RY, false, false, VSIGN>;
 }
 
-template <typename T> const void *step_kernel_ptr(int tile, bool open, bool nonos)
+// The variable-sign option is built for the default launch shapes only
+// (32x24 and 32x32 regions).
+template <typename T, int RX, int RY> static const void *pick(int variant)
+{
+    const bool open = variant & kVariantOpen, nonos = variant & kVariantNonos;
+    if (variant & kVariantVsign) {
+        if constexpr (RX == 32 && (RY == 24 || RY == 32)) return pick4<T, RX, RY, true>(open, nonos);
+        return nullptr;
+    }
+    return pick4<T, RX, RY, false>(open, nonos);
+}
+
+template <typename T> const void *step_kernel_ptr(int tile, int variant)
 {
     switch (tile) {
-    case 1: return pick<T, 64, 16>(open, nonos);
-    case 2: return pick<T, 32, 32>(open, nonos);
-    case 3: return pick<T, 64, 8>(open, nonos);
-    case 4: return pick<T, 32, 16>(open, nonos);
-    case 5: return pick<T, 32, 24>(open, nonos);
-    case 6: return pick<T, 16, 16>(open, nonos);
+    case 1: return pick<T, 64, 16>(variant);
+    case 2: return pick<T, 32, 32>(variant);
+    case 3: return pick<T, 64, 8>(variant);
+    case 4: return pick<T, 32, 16>(variant);
+    case 5: return pick<T, 32, 24>(variant);
+    case 6: return pick<T, 16, 16>(variant);
     default: return nullptr;
     }
 }
 
 template <typename T>
 hipError_t launch_persistent(const GridDesc<T> *grids, const Segment *segs, const int *wg_begin,
-                             int nwg, int tile, bool open, bool nonos, int flip, double eps,
+                             int nwg, int tile, int variant, int flip, double eps,
                              long long *seg_ticks, hipStream_t s)
 {
     int count = 0;
     const TileShape *sh = tile_shapes(&count);
-    const void *k = step_kernel_ptr<T>(tile, open, nonos);
+    const void *k = step_kernel_ptr<T>(tile, variant);
     if (!k || nwg < 1) return hipErrorInvalidValue;
     void *args[] = {(void *)&grids, (void *)&segs, (void *)&wg_begin, (void *)&flip, (void *)&eps,
                     (void *)&seg_ticks};
@@ -807,13 +826,13 @@ template <typename T> hipError_t launch_donor(const DonorArgs<T> &a, bool open, 
     return hipGetLastError();
 }
 
-template const void *step_kernel_ptr<double>(int, bool, bool);
-template const void *step_kernel_ptr<float>(int, bool, bool);
+template const void *step_kernel_ptr<double>(int, int);
+template const void *step_kernel_ptr<float>(int, int);
 template hipError_t launch_persistent<double>(const GridDesc<double> *, const Segment *,
-                                              const int *, int, int, bool, bool, int, double,
+                                              const int *, int, int, int, int, double,
                                               long long *, hipStream_t);
 template hipError_t launch_persistent<float>(const GridDesc<float> *, const Segment *, const int *,
-                                             int, int, bool, bool, int, double, long long *,
+                                             int, int, int, int, double, long long *,
                                              hipStream_t);
 template const void *donor_kernel_ptr<double>(bool);
 template const void *donor_kernel_ptr<float>(bool);

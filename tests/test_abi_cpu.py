@@ -78,6 +78,16 @@ def test_invalid_params_are_rejected(bad):
     assert _lib.mpdata_last_error(None)
 
 
+def test_vsign_flag_needs_a_default_launch_shape():
+    vs = _lib.MPDATA_FLAG_VSIGN
+    assert _lib.mpdata_workspace_bytes(_params(flags=vs)) > 0
+    for t in (2, 5):
+        assert _lib.mpdata_workspace_bytes(_params(flags=vs, tile=t)) > 0
+    for t in (1, 3, 4, 6):
+        assert _lib.mpdata_workspace_bytes(_params(flags=vs, tile=t)) == 0
+    assert _lib.mpdata_workspace_bytes(_params(flags=8)) == 0
+
+
 def test_plane_limit_depends_on_word_size():
     # one x-y plane is addressed with 32-bit byte offsets: 30001^2 words fit
     # in 4 GiB as FP32, not as FP64

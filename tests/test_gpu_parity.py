@@ -238,6 +238,55 @@ def test_fp32_every_tile_agrees(orc):
 
 # ------------------------------------------------------------ full sizes
 
+# ------------------------------------------------- variable-sign option
+
+def _mixed_sign(seed, shape, bc=0):
+    import dataclasses
+    f = inputs.random_smooth(seed, shape, bc=bc)
+    return dataclasses.replace(f, psi=f.psi - 1.0)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("nonos", [True, False])
+def test_vsign_parity_fp64(orc, bc, nonos):
+    """|psi1| in the ratios on a sign-changing field, ragged tiles, 4 steps."""
+    f = _mixed_sign(31, (13, 45, 70), bc)
+    assert f.psi.min() < 0.0 < f.psi.max()
+    want = oracle_run(orc, f, 4, nonos=nonos, vsign=True)
+    got = gpu_run(f, 4, nonos=nonos, vsign=True)
+    assert rel_linf(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_vsign_parity_fp32(orc, bc):
+    f = _mixed_sign(32, (13, 45, 70), bc).astype(np.float32)
+    n = 4
+    want = oracle_run(orc, f.as_f64(), n, vsign=True)
+    got = gpu_run(f, n, dtype=torch.float32, vsign=True)
+    assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
+
+
+def test_vsign_is_the_default_scheme_on_positive_fields():
+    f = inputs.random_smooth(33, (13, 45, 70))
+    assert f.psi.min() > 0.3
+    assert np.array_equal(gpu_run(f, 3, vsign=True), gpu_run(f, 3))
+
+
+def test_vsign_odd_symmetry_bitwise():
+    import dataclasses
+    f = _mixed_sign(34, (13, 45, 70))
+    a = gpu_run(f, 3, nonos=False, vsign=True)
+    b = gpu_run(dataclasses.replace(f, psi=-f.psi), 3, nonos=False, vsign=True)
+    assert np.array_equal(b, -a)
+
+
+def test_vsign_needs_a_default_launch_shape():
+    from paper_1507_01265_amd import _lib
+    f = _mixed_sign(35, (8, 16, 16))
+    with pytest.raises((_lib.MpdataError, ValueError)):
+        gpu_run(f, 1, tile=4, vsign=True)
+
+
 @pytest.mark.slow
 def test_full_size_rotation_fp64(orc):
     """512x256x64, the rotation workload at full size, 2 steps."""
