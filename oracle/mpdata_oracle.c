@@ -32,7 +32,8 @@
  *   - eps regularises every ratio denominator (A, B and beta); default 1e-15.
  *   - the face density is the arithmetic mean of the two cell densities.
  *   - limiter bounds run over psi^n and psi1 at the cell and its 6 face
- *     neighbours (Listing 1 shows the single-field 7-point maximum).
+ *     neighbours (Listing 1 shows the single-field 7-point maximum); a
+ *     further corrective pass adds each further iterate of the step.
  *   - periodic boundaries wrap cell indices; face n along an axis is the
  *     same face as face 0 (the caller supplies equal values).
  *   - open boundaries are zero-gradient: a ghost cell takes the value of
@@ -45,6 +46,11 @@
  * paper cites -- Smolarkiewicz & Margolin 1998): the ratios A and B of S3
  * take |psi1| in place of psi1, so their denominators cannot vanish where
  * the field changes sign; every other stage is unchanged.
+ *
+ * Option iord > 2 (Smolarkiewicz 1984: the corrective pass repeated): pass
+ * k = 2 .. iord-1 runs S3-S7 again on the result psi^(k) of pass k-1, with
+ * the (limited) antidiffusive velocity of pass k-1 in the place of the
+ * Courant numbers; h, eps and the options are the same in every pass.
  *
  * Layout: cell arrays are [k][j][i] with i fastest, nx*ny*nz doubles.
  * Face arrays hold n+1 faces along their own axis: u1[k][j][i'] with
@@ -252,11 +258,14 @@ static void pseudo_velocities(const grid *g, const double *p, const double *u1,
 }
 
 /* ------------------------------------------------------------ S4: bounds
- * mx_c (mn_c) is the maximum (minimum) of psi^n and psi1 over the cell and
- * its six face neighbours -- the paper's stage 8 (Listing 1) is this 7-point
- * maximum for one field; Smolarkiewicz & Grabowski 1990 take it over both
- * the old solution and the first-order solution. */
-static void bounds(const grid *g, const double *pn, const double *p1, double *mx,
+ * mx_c (mn_c) is the maximum (minimum), over the cell and its six face
+ * neighbours, of every field in fields[0 .. nf-1] -- the paper's stage 8
+ * (Listing 1) is this 7-point maximum for one field.  Smolarkiewicz &
+ * Grabowski 1990 take it over the old solution and the first-order one; a
+ * later corrective pass adds each further iterate of the step, so the
+ * fields are psi^n, psi^(1), ..., psi^(k) for the pass that corrects
+ * psi^(k). */
+static void bounds(const grid *g, const double *const *fields, int nf, double *mx,
                    double *mn)
 {
     static const int off[7][3] = {{0, 0, 0},  {-1, 0, 0}, {1, 0, 0}, {0, -1, 0},
@@ -269,8 +278,10 @@ static void bounds(const grid *g, const double *pn, const double *p1, double *mx
                 double hi = -INFINITY, lo = INFINITY;
                 for (int q = 0; q < 7; ++q) {
                     long o = cell(g, i + off[q][0], j + off[q][1], k + off[q][2]);
-                    hi = fmax(hi, fmax(pn[o], p1[o]));
-                    lo = fmin(lo, fmin(pn[o], p1[o]));
+                    for (int f = 0; f < nf; ++f) {
+                        hi = fmax(hi, fields[f][o]);
+                        lo = fmin(lo, fields[f][o]);
+                    }
                 }
                 mx[cell(g, i, j, k)] = hi;
                 mn[cell(g, i, j, k)] = lo;
@@ -362,7 +373,7 @@ int orc_check(const orc_params *p)
     if (!p) return -1;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
     if (p->bc != ORC_BC_PERIODIC && p->bc != ORC_BC_OPEN) return -1;
-    if (p->iord != 1 && p->iord != 2) return -1;
+    if (p->iord < 1 || p->iord > ORC_MAX_IORD) return -1;
     if (p->nonos != 0 && p->nonos != 1) return -1;
     if (p->vsign != 0 && p->vsign != 1) return -1;
     if (!(p->eps > 0.0)) return -1;
@@ -379,53 +390,77 @@ int orc_step(const orc_params *p, const double *psi, const double *u1,
     long n1 = (long)(p->nx + 1) * p->ny * p->nz;
     long n2 = (long)p->nx * (p->ny + 1) * p->nz;
     long n3 = (long)p->nx * p->ny * (p->nz + 1);
+    const int npass = p->iord - 1;  /* corrective passes */
 
-    double *p1 = malloc(sizeof(double) * n);
-    if (!p1) return -2;
-    donor_cell_pass(&g, psi, u1, u2, u3, h, p1);            /* S1+S2 */
-    if (st && st->psi1) memcpy(st->psi1, p1, sizeof(double) * n);
-    if (p->iord == 1) {
-        memcpy(out, p1, sizeof(double) * n);
-        free(p1);
-        return 0;
+    /* iterates of the step: it[0] = psi^n, it[k] = psi^(k) */
+    const double *it[ORC_MAX_IORD + 1];
+    double *own[ORC_MAX_IORD + 1] = {0};
+    /* velocities: the pass being corrected (c) and the new one (v) */
+    double *va[3] = {0}, *vb[3] = {0};
+    double *mx = 0, *mn = 0, *bu = 0, *bd = 0, *a1 = 0;
+    int rc = -2;
+    it[0] = psi;
+    for (int k = 1; k <= p->iord; ++k)
+        if (!(own[k] = malloc(sizeof(double) * n))) goto done;
+    if (npass > 0) {
+        long nf[3] = {n1, n2, n3};
+        for (int d = 0; d < 3; ++d)
+            if (!(va[d] = malloc(sizeof(double) * nf[d])) ||
+                !(vb[d] = malloc(sizeof(double) * nf[d])))
+                goto done;
+        if (!(mx = malloc(sizeof(double) * n)) || !(mn = malloc(sizeof(double) * n)) ||
+            !(bu = malloc(sizeof(double) * n)) || !(bd = malloc(sizeof(double) * n)))
+            goto done;
+        if (p->vsign && !(a1 = malloc(sizeof(double) * n))) goto done;
     }
 
-    double *v1 = malloc(sizeof(double) * n1), *v2 = malloc(sizeof(double) * n2),
-           *v3 = malloc(sizeof(double) * n3);
-    double *mx = malloc(sizeof(double) * n), *mn = malloc(sizeof(double) * n);
-    double *bu = malloc(sizeof(double) * n), *bd = malloc(sizeof(double) * n);
-    if (!v1 || !v2 || !v3 || !mx || !mn || !bu || !bd) {
-        free(p1); free(v1); free(v2); free(v3); free(mx); free(mn); free(bu); free(bd);
-        return -2;
-    }
-    if (p->vsign) {
-        /* S3 on |psi1| (option vsign); the limiter and S7 keep psi1 */
-        double *a1 = malloc(sizeof(double) * n);
-        if (!a1) {
-            free(p1); free(v1); free(v2); free(v3); free(mx); free(mn); free(bu); free(bd);
-            return -2;
+    donor_cell_pass(&g, psi, u1, u2, u3, h, own[1]);                  /* S1+S2 */
+    it[1] = own[1];
+    if (st && st->psi1) memcpy(st->psi1, own[1], sizeof(double) * n);
+
+    /* Corrective pass k (k = 1 .. iord-1) corrects psi^(k): its velocity
+     * field is the Courant numbers for k = 1 and the (limited)
+     * antidiffusive velocity of pass k-1 after that (Smolarkiewicz 1984). */
+    const double *c1 = u1, *c2 = u2, *c3 = u3;
+    for (int k = 1; k <= npass; ++k) {
+        const double *cur = it[k];
+        double **v = (k & 1) ? va : vb;
+        if (p->vsign) {
+            /* S3 on |psi^(k)| (option vsign); the limiter and S7 keep psi^(k) */
+            for (long c = 0; c < n; ++c) a1[c] = fabs(cur[c]);
+            pseudo_velocities(&g, a1, c1, c2, c3, h, p->eps, v[0], v[1], v[2]);
+        } else {
+            pseudo_velocities(&g, cur, c1, c2, c3, h, p->eps, v[0], v[1], v[2]);   /* S3 */
         }
-        for (long c = 0; c < n; ++c) a1[c] = fabs(p1[c]);
-        pseudo_velocities(&g, a1, u1, u2, u3, h, p->eps, v1, v2, v3);
-        free(a1);
-    } else {
-        pseudo_velocities(&g, p1, u1, u2, u3, h, p->eps, v1, v2, v3);   /* S3 */
+        const int last = k == npass;
+        if (last && st && st->v1) memcpy(st->v1, v[0], sizeof(double) * n1);
+        if (last && st && st->v2) memcpy(st->v2, v[1], sizeof(double) * n2);
+        if (last && st && st->v3) memcpy(st->v3, v[2], sizeof(double) * n3);
+        if (p->nonos) {
+            bounds(&g, it, k + 1, mx, mn);                                        /* S4 */
+            limiter_factors(&g, cur, v[0], v[1], v[2], mx, mn, h, p->eps, bu, bd); /* S5 */
+            if (last && st && st->mx) memcpy(st->mx, mx, sizeof(double) * n);
+            if (last && st && st->mn) memcpy(st->mn, mn, sizeof(double) * n);
+            if (last && st && st->beta_up) memcpy(st->beta_up, bu, sizeof(double) * n);
+            if (last && st && st->beta_dn) memcpy(st->beta_dn, bd, sizeof(double) * n);
+            limit_velocities(&g, bu, bd, v[0], v[1], v[2]);                       /* S6 */
+        }
+        donor_cell_pass(&g, cur, v[0], v[1], v[2], h, own[k + 1]);                /* S7 */
+        it[k + 1] = own[k + 1];
+        c1 = v[0];
+        c2 = v[1];
+        c3 = v[2];
     }
-    if (st && st->v1) memcpy(st->v1, v1, sizeof(double) * n1);
-    if (st && st->v2) memcpy(st->v2, v2, sizeof(double) * n2);
-    if (st && st->v3) memcpy(st->v3, v3, sizeof(double) * n3);
-    if (p->nonos) {
-        bounds(&g, psi, p1, mx, mn);                                     /* S4 */
-        limiter_factors(&g, p1, v1, v2, v3, mx, mn, h, p->eps, bu, bd);  /* S5 */
-        if (st && st->mx) memcpy(st->mx, mx, sizeof(double) * n);
-        if (st && st->mn) memcpy(st->mn, mn, sizeof(double) * n);
-        if (st && st->beta_up) memcpy(st->beta_up, bu, sizeof(double) * n);
-        if (st && st->beta_dn) memcpy(st->beta_dn, bd, sizeof(double) * n);
-        limit_velocities(&g, bu, bd, v1, v2, v3);                        /* S6 */
+    memcpy(out, it[p->iord], sizeof(double) * n);
+    rc = 0;
+done:
+    for (int k = 1; k <= p->iord; ++k) free(own[k]);
+    for (int d = 0; d < 3; ++d) {
+        free(va[d]);
+        free(vb[d]);
     }
-    donor_cell_pass(&g, p1, v1, v2, v3, h, out);                         /* S7 */
-    free(p1); free(v1); free(v2); free(v3); free(mx); free(mn); free(bu); free(bd);
-    return 0;
+    free(mx); free(mn); free(bu); free(bd); free(a1);
+    return rc;
 }
 
 int orc_run(const orc_params *p, double *psi, const double *u1, const double *u2,

@@ -12,17 +12,19 @@ extern "C" {
 #endif
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OPEN = 1 };
+enum { ORC_MAX_IORD = 16 };
 
 typedef struct {
     int nx, ny, nz; /* cells along x (fastest), y, z */
     int bc;         /* ORC_BC_PERIODIC or ORC_BC_OPEN */
-    int iord;       /* 1: donor cell only; 2: one corrective pass */
+    int iord;       /* 1: donor cell only; k > 1: k - 1 corrective passes */
     int nonos;      /* 1: non-oscillatory limiter on */
     int vsign;      /* 1: fields of variable sign -- |psi1| in the ratios A, B */
     double eps;     /* regulariser of ratio denominators */
 } orc_params;
 
-/* Optional stage outputs of one step (any pointer may be NULL). */
+/* Optional stage outputs of one step (any pointer may be NULL): psi1 is the
+ * first-order result, the others belong to the last corrective pass. */
 typedef struct {
     double *psi1;               /* nx*ny*nz */
     double *v1, *v2, *v3;       /* unlimited pseudo-velocities, face arrays */

@@ -31,16 +31,19 @@ MUTANTS = {
     "upwind_wrong_face": ("c1[xface(g, i + 1, j, k)]);\n                double f2lo",
                           "c1[xface(g, i, j, k)]);\n                double f2lo"),
     "bounds_wrong_neighbour": ("{0, 0, 0},  {-1, 0, 0}, {1, 0, 0}", "{0, 0, 0},  {-1, 0, 0}, {-1, 0, 0}"),
-    "bounds_one_field": ("hi = fmax(hi, fmax(pn[o], p1[o]));", "hi = fmax(hi, pn[o]);"),
+    "bounds_one_field": ("bounds(&g, it, k + 1, mx, mn);", "bounds(&g, it, 1, mx, mn);"),
     "limiter_factors_swapped": ("return fmin(1.0, fmin(bdn_a, bup_b)) * pos(v)",
                                 "return fmin(1.0, fmin(bup_a, bdn_b)) * pos(v)"),
     "inflow_sign": ("double in = ((pos(x_lo) - neg(x_hi))", "double in = ((pos(x_lo) + neg(x_hi))"),
     "beta_without_h": ("bup[c] = (mx[c] - pc) * h[c] / (in + eps);", "bup[c] = (mx[c] - pc) / (in + eps);"),
     "mass_drops_errors": ("c = c + (perr + serr);", "c = c + serr;"),
-    "vsign_ignored": ("for (long c = 0; c < n; ++c) a1[c] = fabs(p1[c]);",
-                      "for (long c = 0; c < n; ++c) a1[c] = p1[c];"),
-    "vsign_in_corrective_pass": ("donor_cell_pass(&g, p1, v1, v2, v3, h, out);                         /* S7 */",
-                                 "for (long c = 0; c < n; ++c) p1[c] = fabs(p1[c]);\n    donor_cell_pass(&g, p1, v1, v2, v3, h, out);"),
+    "vsign_ignored": ("for (long c = 0; c < n; ++c) a1[c] = fabs(cur[c]);",
+                      "for (long c = 0; c < n; ++c) a1[c] = cur[c];"),
+    "later_pass_keeps_courant": ("        c1 = v[0];\n        c2 = v[1];\n        c3 = v[2];\n", ""),
+    "bounds_not_cumulative": ("bounds(&g, it, k + 1, mx, mn);",
+                              "const double *two[2] = {psi, cur};\n            bounds(&g, two, 2, mx, mn);"),
+    "vsign_in_corrective_pass": ("donor_cell_pass(&g, cur, v[0], v[1], v[2], h, own[k + 1]);",
+                                 "donor_cell_pass(&g, p->vsign ? a1 : cur, v[0], v[1], v[2], h, own[k + 1]);"),
 }
 
 
@@ -62,6 +65,8 @@ def _checks():
     out["vsign_positive"] = lambda: pins.test_vsign_is_the_default_scheme_on_positive_fields(oracle)
     out["vsign_odd"] = lambda: pins.test_vsign_odd_symmetry_bitwise(oracle)
     out["vsign_wave"] = lambda: pins.test_vsign_advects_a_sign_changing_wave(oracle)
+    out["iord3_bounds"] = lambda: pins.test_more_passes_bound_over_every_iterate(oracle)
+    out["iord3_error_1d"] = lambda: pins.test_a_second_pass_reduces_the_error_1d(oracle, 0.0)
     return out
 
 
