@@ -80,8 +80,10 @@ def measured_traffic(workload):
         if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_1507_01265_amd", "csrc", "mpdata_step.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    # the step kernel's source: the march and the kernel file, concatenated
+    csrc = os.path.join(ROOT, "paper_1507_01265_amd", "csrc")
+    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                  for f in ("mpdata_march.h", "mpdata_step.hip"))).hexdigest()
     if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])

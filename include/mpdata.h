@@ -77,8 +77,15 @@ typedef struct {
                              is addressed with 32-bit byte offsets) */
     int32_t dtype;        /* MPDATA_FP64 or MPDATA_FP32 */
     int32_t bc;           /* MPDATA_BC_PERIODIC or MPDATA_BC_OPEN (all axes) */
-    int32_t iord;         /* 1: donor cell only; 2: one corrective pass */
-    int32_t nonos;        /* 1: non-oscillatory limiter on (needs iord 2) */
+    int32_t iord;         /* 1: donor cell only; k = 2 .. 16: k - 1 corrective
+                             passes (Smolarkiewicz 1984: pass j > 1 corrects
+                             the result of pass j - 1 with the limited
+                             velocity of pass j - 1 as its Courant numbers;
+                             its limiter bounds run over psi^n and every
+                             iterate of the step).  iord > 2 needs the
+                             default launch shape (tile 0) and runs on
+                             single-grid contexts only */
+    int32_t nonos;        /* 1: non-oscillatory limiter on (needs iord >= 2) */
     int32_t tile;         /* launch shape: 0 = library default, else an id
                              from mpdata_tile_count()/mpdata_tile_info() */
     int32_t flags;        /* MPDATA_FLAG_* bits, 0 = defaults */
@@ -92,7 +99,9 @@ typedef struct mpdata_ctx mpdata_ctx; /* opaque */
 
 /* Bytes of workspace mpdata_create() needs for these parameters (0 if they
  * are invalid).  The workspace holds the second psi buffer of the time loop
- * and the mass-reduction partials. */
+ * and the mass-reduction partials; with iord > 2 also the intermediate
+ * iterates, the limited velocities (face arrays) and, with the limiter, the
+ * running bounds of the corrective passes (one set; two from iord 4 on). */
 size_t mpdata_workspace_bytes(const mpdata_params *p);
 
 /* Validates the parameters and arrays and binds them to a new context.
@@ -113,7 +122,9 @@ int mpdata_create(const mpdata_params *p, void *psi, const void *u1, const void 
  * the state after the steps (an odd step count ends with one device copy
  * from the workspace into psi).  Each step is one launch of the persistent
  * fused kernel over a plan of (tile, z-range) segments balanced across the
- * GPU; runs of steps are replayed from a hipGraph built on first use. */
+ * GPU (iord 2; runs of steps are replayed from a hipGraph built on first
+ * use), or a chain of iord - 1 launches of it over the same plan (iord > 2:
+ * the fused step, then one launch per further corrective pass). */
 int mpdata_step(mpdata_ctx *ctx, int32_t nsteps);
 
 /* Mass M = sum over cells of h*psi with a compensated (double-double)

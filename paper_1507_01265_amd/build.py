@@ -18,8 +18,8 @@ LIB = os.path.join(HERE, "libmpdata.so")
 # (source, extra flags): the step kernels assume finite inputs (no NaN
 # semantics, so min/max need no operand canonicalisation); the mass and
 # validation kernels keep IEEE semantics because they detect NaN/Inf.
-SOURCES = [("mpdata_step.hip", ["-fno-honor-nans"]), ("mpdata_reduce.hip", []),
-           ("mpdata_abi.hip", [])]
+SOURCES = [("mpdata_step.hip", ["-fno-honor-nans"]), ("mpdata_pass.hip", ["-fno-honor-nans"]),
+           ("mpdata_reduce.hip", []), ("mpdata_abi.hip", [])]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -30,15 +30,19 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    """Compile every source (in parallel) and link libmpdata.so."""
+    objs, procs = [], []
     for src, extra in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
         cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -29,6 +29,7 @@ constexpr int kGraphSteps = 8;    // steps per replayed graph (even: psi ends wh
 constexpr int kXcds = 8;          // XCDs of an MI355X; workgroup w runs on XCD w % 8
 constexpr int kMinShare = 24;     // fewest planes a workgroup's share of a plan marches
 constexpr int kPipelineFill = 4;  // march iterations before a segment's first output plane
+constexpr int kMaxIord = 16;      // most passes of one step (1 donor-cell + 15 corrective)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -71,15 +72,17 @@ const char *check_params(const mpdata_params *p)
     if ((double)(p->nx + 1) * (p->ny + 1) * (p->dtype == MPDATA_FP64 ? 8 : 4) >= 4294967296.0)
         return "x-y plane too large (>= 4 GiB)";
     if (p->bc != MPDATA_BC_PERIODIC && p->bc != MPDATA_BC_OPEN) return "bc must be PERIODIC or OPEN";
-    if (p->iord != 1 && p->iord != 2) return "iord must be 1 or 2";
+    if (p->iord < 1 || p->iord > kMaxIord) return "iord must be 1 .. 16";
     if (p->nonos != 0 && p->nonos != 1) return "nonos must be 0 or 1";
-    if (p->nonos && p->iord != 2) return "nonos needs iord 2";
+    if (p->nonos && p->iord < 2) return "nonos needs iord >= 2";
     if (!(p->eps > 0.0) || !isfinite(p->eps)) return "eps must be finite and > 0";
     if (p->flags & ~(MPDATA_FLAG_NO_GRAPH | MPDATA_FLAG_VSIGN)) return "unknown flag bits";
     if (p->reserved != 0) return "reserved must be 0";
     int count = 0;
     mpd::tile_shapes(&count);
     if (p->tile < 0 || p->tile > count) return "tile id out of range";
+    if (p->iord > 2 && p->tile != 0 && p->tile != default_tile(p->dtype, p->bc))
+        return "iord > 2 runs on the default launch shape (tile 0)";
     if ((p->flags & MPDATA_FLAG_VSIGN) && p->tile != 0 &&
         (shape_of(p->tile).rx != 32 || (shape_of(p->tile).ry != 24 && shape_of(p->tile).ry != 32)))
         return "the variable-sign option runs on the 32x24 and 32x32 launch shapes (tile 0, 2 or 5)";
@@ -256,12 +259,17 @@ const char *check_plan(const std::vector<mpdata_params> &grids, int tile,
 }
 
 struct Layout {
-    size_t psi2, grids, segs, wg, ticks, partials, result, flags, total;
+    size_t psi2, grids, segs, wg, ticks, partials, result, flags;
+    // a single grid with iord > 2: the buffers of the chain of corrective
+    // passes (iterates, limited velocities, running bounds, two sets used in
+    // turn) and the descriptors of its launches for both step parities
+    size_t it[2], w[2][3], bmx[2], bmn[2], pass_grids, pass_io;
+    size_t total;
 };
 
 Layout layout_for(const std::vector<mpdata_params> &grids, int max_segs, int max_wg)
 {
-    Layout l;
+    Layout l{};
     size_t off = 0;
     l.psi2 = off;
     for (const mpdata_params &p : grids) off += align_up(cells_of(&p) * word_of(&p));
@@ -279,6 +287,30 @@ Layout layout_for(const std::vector<mpdata_params> &grids, int max_segs, int max
     off += align_up(2 * sizeof(double));
     l.flags = off;
     off += align_up(4 * sizeof(unsigned int));
+    if (grids.size() == 1 && grids[0].iord > 2) {
+        const mpdata_params &p = grids[0];
+        const size_t w = word_of(&p), nx = p.nx, ny = p.ny, nz = p.nz;
+        const size_t faces[3] = {(nx + 1) * ny * nz, nx * (ny + 1) * nz, nx * ny * (nz + 1)};
+        const int sets = p.iord > 3 ? 2 : 1;  // a second set only for a middle pass
+        for (int s = 0; s < sets; ++s) {
+            l.it[s] = off;
+            off += align_up(cells_of(&p) * w);
+            for (int d = 0; d < 3; ++d) {
+                l.w[s][d] = off;
+                off += align_up(faces[d] * w);
+            }
+            if (p.nonos) {
+                l.bmx[s] = off;
+                off += align_up(cells_of(&p) * w);
+                l.bmn[s] = off;
+                off += align_up(cells_of(&p) * w);
+            }
+        }
+        l.pass_grids = off;
+        off += align_up(2 * (size_t)(p.iord - 1) * sizeof(mpd::GridDesc<double>));
+        l.pass_io = off;
+        off += align_up(2 * (size_t)(p.iord - 1) * sizeof(mpd::PassIO<double>));
+    }
     l.total = off;
     return l;
 }
@@ -366,6 +398,25 @@ static hipError_t launch_one(Engine &e, int flip, long long *ticks)
     }
     const mpd::Segment *segs = (const mpd::Segment *)(e.ws + e.lay.segs);
     const int *wg = (const int *)(e.ws + e.lay.wg);
+    if (e.iord > 2) {
+        // the chain of corrective passes of one step: head, middle passes, last
+        const int npass = e.iord - 1;
+        for (int j = 0; j < npass; ++j) {
+            const int mode = j == 0 ? mpd::kPassHead : (j == npass - 1 ? mpd::kPassLast : mpd::kPassMid);
+            const size_t i = (size_t)flip * npass + j;
+            const auto *gd = (const mpd::GridDesc<double> *)(e.ws + e.lay.pass_grids) + i;
+            const auto *io = (const mpd::PassIO<double> *)(e.ws + e.lay.pass_io) + i;
+            const hipError_t r =
+                e.dtype == MPDATA_FP32
+                    ? mpd::launch_pass<float>((const mpd::GridDesc<float> *)gd,
+                                              (const mpd::PassIO<float> *)io, segs, wg, e.nwg,
+                                              e.tile, e.variant, mode, e.eps, e.stream)
+                    : mpd::launch_pass<double>(gd, io, segs, wg, e.nwg, e.tile, e.variant, mode,
+                                               e.eps, e.stream);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
     if (e.dtype == MPDATA_FP32)
         return mpd::launch_persistent<float>((const mpd::GridDesc<float> *)(e.ws + e.lay.grids),
                                              segs, wg, e.nwg, e.tile, e.variant, flip,
@@ -464,6 +515,47 @@ static int engine_mass(Engine &e, int i, double *out)
     return MPDATA_OK;
 }
 
+// Descriptors of the chain of corrective passes (iord > 2) for both step
+// parities f: pass j reads psi[f] (j = 0) or iterate set (j-1) mod 2 and
+// writes psi[1-f] (the last pass) or iterate set j mod 2; its velocity field
+// is the Courant numbers (j = 0) or the limited velocity of pass j-1, its
+// running bounds those written by pass j-1.  FP32 reinterprets the pointers.
+static void pass_descriptors(const Engine &e, std::vector<mpd::GridDesc<double>> &pg,
+                             std::vector<mpd::PassIO<double>> &pio)
+{
+    const int npass = e.iord - 1;
+    const mpd::GridDesc<double> &g = e.grids[0];
+    auto at = [&](size_t off) { return (double *)(e.ws + off); };
+    pg.assign(2 * npass, g);
+    pio.assign(2 * npass, mpd::PassIO<double>{});
+    for (int f = 0; f < 2; ++f)
+        for (int j = 0; j < npass; ++j) {
+            mpd::GridDesc<double> &d = pg[f * npass + j];
+            mpd::PassIO<double> &io = pio[f * npass + j];
+            const int in = (j - 1) & 1, out = j & 1;
+            if (j > 0) {
+                d.u1 = at(e.lay.w[in][0]);
+                d.u2 = at(e.lay.w[in][1]);
+                d.u3 = at(e.lay.w[in][2]);
+                if (e.nonos) {
+                    io.bmx = at(e.lay.bmx[in]);
+                    io.bmn = at(e.lay.bmn[in]);
+                }
+            }
+            d.psi[0] = j == 0 ? g.psi[f] : at(e.lay.it[in]);
+            d.psi[1] = j == npass - 1 ? g.psi[1 - f] : at(e.lay.it[out]);
+            if (j < npass - 1) {
+                io.w1 = at(e.lay.w[out][0]);
+                io.w2 = at(e.lay.w[out][1]);
+                io.w3 = at(e.lay.w[out][2]);
+                if (e.nonos) {
+                    io.mx = at(e.lay.bmx[out]);
+                    io.mn = at(e.lay.bmn[out]);
+                }
+            }
+        }
+}
+
 // Validates every grid's arrays on the device (h > 0 and finite; periodic
 // faces n == 0), lays out the workspace, uploads descriptors and the plan.
 static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *params,
@@ -533,6 +625,9 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
     }
     if (const char *m = check_plan(e.params, e.tile, segs, wg))
         return fail_to(errbuf, MPDATA_EINVAL, "plan: %s", m);
+    if (e.iord > 2 && !(e.dtype == MPDATA_FP32 ? mpd::pass_kernel_ptr<float>(e.tile, e.variant, mpd::kPassHead)
+                                               : mpd::pass_kernel_ptr<double>(e.tile, e.variant, mpd::kPassHead)))
+        return fail_to(errbuf, MPDATA_ENOTSUP, "no kernels of further corrective passes for this launch shape");
     e.nwg = (int)wg.size() - 1;
     e.nseg = (int)segs.size();
     e.lay = layout_for(e.params, e.nseg, e.nwg);
@@ -587,6 +682,17 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
     if (r == hipSuccess)
         r = hipMemcpyAsync(e.ws + e.lay.wg, wg.data(), wg.size() * sizeof(int),
                            hipMemcpyHostToDevice, e.stream);
+    std::vector<mpd::GridDesc<double>> pg;
+    std::vector<mpd::PassIO<double>> pio;
+    if (e.iord > 2) {
+        pass_descriptors(e, pg, pio);
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(e.ws + e.lay.pass_grids, pg.data(), pg.size() * sizeof(pg[0]),
+                               hipMemcpyHostToDevice, e.stream);
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(e.ws + e.lay.pass_io, pio.data(), pio.size() * sizeof(pio[0]),
+                               hipMemcpyHostToDevice, e.stream);
+    }
     if (r == hipSuccess) r = hipStreamSynchronize(e.stream);
     if (r != hipSuccess) return fail_to(errbuf, MPDATA_EDEVICE, "plan upload: %s", hipGetErrorString(r));
     return MPDATA_OK;

@@ -14,6 +14,16 @@ template <typename T> struct GridDesc {
     int nx, ny, nz, pad;
 };
 
+// The extra arrays of one launch in a chain of corrective passes (a step
+// with iord > 2): bmx, bmn are the running bounds of the earlier iterates
+// (cell arrays, read by a further pass); w1, w2, w3 the limited
+// antidiffusive velocity of the launch (face arrays) and mx, mn its running
+// bounds (cell arrays), both written for the next pass.
+template <typename T> struct PassIO {
+    const T *bmx, *bmn;
+    T *w1, *w2, *w3, *mx, *mn;
+};
+
 // A piece of work of the persistent step kernel: output tile (tx, ty) of a
 // grid over the planes [z0, z1).
 struct Segment {
@@ -39,6 +49,19 @@ template <typename T>
 hipError_t launch_persistent(const GridDesc<T> *grids, const Segment *segs, const int *wg_begin,
                              int nwg, int tile, int variant, int flip, double eps,
                              long long *seg_ticks, hipStream_t s);
+
+// Launches of a chain of corrective passes (iord > 2), one grid each:
+// grids[0].psi[0] -> grids[0].psi[1] with the arrays of io[0].  mode is
+// the march mode (head: the time step plus velocity and bounds out; mid: a
+// further pass with velocity and bounds out; last: the final pass).  Built
+// for the default launch shape of each precision and boundary mode; the
+// pointer is nullptr for other shapes.
+enum { kPassHead = 1, kPassMid = 2, kPassLast = 3 };
+template <typename T> const void *pass_kernel_ptr(int tile, int variant, int mode);
+template <typename T>
+hipError_t launch_pass(const GridDesc<T> *grids, const PassIO<T> *io, const Segment *segs,
+                       const int *wg_begin, int nwg, int tile, int variant, int mode, double eps,
+                       hipStream_t s);
 
 // Donor-cell pass only (iord 1), one grid: psi[flip] -> psi[1 - flip].
 template <typename T> struct DonorArgs {

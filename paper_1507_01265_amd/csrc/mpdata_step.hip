@@ -1,696 +1,13 @@
-// mpdata_step.hip -- the fused MPDATA time-step kernel for gfx950.
-//
-// One time step (paper, section 5.2: a chain of dependent stencil stages
-// turning five input matrices into one output; the equations are those of
-// the MPDATA literature the paper cites: donor-cell pass and antidiffusive
-// pseudo-velocities of Smolarkiewicz 1984, non-oscillatory limiter of
-// Smolarkiewicz & Grabowski 1990, density weighting of Smolarkiewicz &
-// Margolin 1998):
-//   S1+S2  psi1 = psi - sum_d dF_d / h,  F = donor(psi_lo, psi_hi, U)
-//   S3     V on every face from psi1, U, h (A ratio, cross terms B, G)
-//   S4     mx, mn = max/min of psi and psi1 over the 7-point neighbourhood
-//   S5     beta_up = (mx - psi1) h / (IN + eps), beta_dn = (psi1 - mn) h / (OUT + eps)
-//   S6     Vt = min(1, bdn_lo, bup_hi) pos(V) + min(1, bup_lo, bdn_hi) neg(V)
-//   S7     psi_out = psi1 - sum_d dFC_d / h,  FC = donor(psi1_lo, psi1_hi, Vt)
-//
-// Fusion (the paper's (3+1)D decomposition, section 5.3: tile the domain
-// and fuse the stage loop so intermediates stay on chip, paying with halo
-// recompute), recast for CDNA:
-//  * a workgroup owns an RX x RY region of x-y columns (its output tile plus
-//    a 2-cell halo) and marches along z through a chunk of planes;
-//  * a thread owns one column and keeps its z-history in registers;
-//    in-plane neighbours are exchanged through LDS planes padded by one
-//    cell on every side, so neighbour offsets are compile-time constants;
-//  * the stage pipeline is skewed in z: iteration t computes psi1 at plane
-//    t, V, the bounds and the limiter factors at plane t-1 (and V3 on face
-//    t), the limited corrective fluxes at plane t-2 and the output at plane
-//    t-3, with three workgroup barriers per iteration (each LDS buffer is
-//    written in the phase after its last read); the march is unrolled by
-//    three so the three psi1 planes sit in fixed LDS slots;
-//  * psi^n and u3 of plane t+2 and the other inputs of plane t+1 are
-//    prefetched into registers.
-// Only psi^{n+1} is written to HBM: 5 array reads + 1 write per cell-step.
-//
-// This translation unit is compiled without NaN semantics (finite inputs
-// are a precondition of the step; mpdata_mass reports NaN/Inf in psi).
-//
-// Boundaries: periodic wraps cell indices (face n == face 0); open is
-// zero-gradient (ghost cells equal the nearest interior cell; reads of
-// cell-centred neighbours at the domain edge are redirected to the cell
-// itself) with zero antidiffusive velocity on boundary-normal faces.
+// mpdata_step.hip -- the persistent fused step kernels (one MPDATA time
+// step per launch; the march they run is in mpdata_march.h) and the
+// donor-cell kernel of iord 1, with their launchers.
 #include <hip/hip_runtime.h>
-#include <stdint.h>
 
 #include <type_traits>
 
-#include "mpdata_kernels.h"
+#include "mpdata_march.h"
 
 namespace mpd {
-
-// ------------------------------------------------------------ index helpers
-
-__device__ __forceinline__ int wrapi(int i, int n)
-{
-    int r = i % n;
-    return r < 0 ? r + n : r;
-}
-
-__device__ __forceinline__ int clampi(int i, int lo, int hi)
-{
-    return i < lo ? lo : (i > hi ? hi : i);
-}
-
-template <bool OPEN> __device__ __forceinline__ int cell_of(int i, int n)
-{
-    return OPEN ? clampi(i, 0, n - 1) : wrapi(i, n);
-}
-
-// face below / above position i along an axis of n cells (face index 0..n)
-template <bool OPEN> __device__ __forceinline__ int face_lo(int i, int n)
-{
-    return OPEN ? clampi(i, 0, n) : wrapi(i, n);
-}
-
-template <bool OPEN> __device__ __forceinline__ int face_hi(int i, int n)
-{
-    return OPEN ? clampi(i + 1, 0, n) : wrapi(i, n) + 1;
-}
-
-// ---------------------------------------------------------------- arithmetic
-
-template <typename T> __device__ __forceinline__ T pos(T x) { return fmax(x, T(0)); }
-template <typename T> __device__ __forceinline__ T neg(T x) { return fmin(x, T(0)); }
-
-// donor-cell flux through a face with lower value l, upper value r:
-// pos(c) l + neg(c) r, evaluated as c times the upwind value (the same
-// number: one of the two products is an exact zero)
-template <typename T> __device__ __forceinline__ T donor(T l, T r, T c)
-{
-    return c * (c > T(0) ? l : r);
-}
-
-// Reciprocal by the hardware estimate (v_rcp_f64 is good to about 2^-24,
-// v_rcp_f32 to 1 ulp) refined with Newton-Raphson steps r <- r + r (1 - x r):
-// two for FP64, one for FP32, which leaves it correctly rounded or within one
-// unit in the last place for the positive, normal operands used here.
-__device__ __forceinline__ double rcp_nr(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-
-__device__ __forceinline__ float rcp_nr(float x)
-{
-    float r = __builtin_amdgcn_rcpf(x);
-    float e = fmaf(-x, r, 1.0f);
-    return fmaf(r, e, r);
-}
-
-// Quotient: a reciprocal good to a few ulps (v_rcp_f64 plus one
-// Newton-Raphson step; v_rcp_f32 alone is within 1 ulp) and one residual
-// correction q <- q + r (n - d q), which squares the relative error away.
-__device__ __forceinline__ double div_nr(double n, double d)
-{
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(r, fma(-d, r, 1.0), r);
-    const double q = n * r;
-    return fma(fma(-d, q, n), r, q);
-}
-
-__device__ __forceinline__ float div_nr(float n, float d)
-{
-    const float r = __builtin_amdgcn_rcpf(d);
-    const float q = n * r;
-    return fmaf(fmaf(-d, q, n), r, q);
-}
-
-template <typename T> struct Tiny;
-template <> struct Tiny<double> { static constexpr double v = 2.2250738585072014e-308; };
-template <> struct Tiny<float> { static constexpr float v = 1.17549435e-38f; };
-
-// Antidiffusive pseudo-velocity on a face between lower cell a and upper
-// cell b (face-normal Courant number U, hs = h_a + h_b; us, ut = sums of the
-// four transverse Courant numbers of a and b along the transverse axes s
-// and t; s_hi = psi1_b,s+1 + psi1_a,s+1 and s_lo likewise one cell down, the
-// same for t).  The definition
-//   V = (|U| - U^2/G) A - (U/G) (Us Bs + Ut Bt),  G = hs/2,
-//   A = (pb - pa)/(pb + pa + eps),  Bs = (s_hi - s_lo)/(2 (s_hi + s_lo + eps)),
-//   Us = us/4 (and t likewise)
-// is evaluated over one common denominator, so a face costs one division:
-//   V = [(|U| hs - 2U^2) nA dBs dBt - (U dA/4)(us nBs dBt + ut nBt dBs)]
-//       / (hs dA dBs dBt).
-// A denominator below the smallest normal number (all neighbouring psi1
-// within eps of zero, possible in FP32 only) gives V = 0.
-template <typename T>
-__device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi, T s_lo, T ut,
-                                             T t_hi, T t_lo, T eps)
-{
-    const T nA = pb - pa, dA = (pb + pa) + eps;
-    const T nBs = s_hi - s_lo, dBs = (s_hi + s_lo) + eps;
-    const T nBt = t_hi - t_lo, dBt = (t_hi + t_lo) + eps;
-    const T P = dBs * dBt;
-    const T c = fabs(U) * hs - T(2) * (U * U);
-    const T cross = (us * nBs) * dBt + (ut * nBt) * dBs;
-    const T num = (c * nA) * P - (T(0.25) * U * dA) * cross;
-    const T den = (hs * dA) * P;
-    if constexpr (sizeof(T) == 8) {
-        // FP64: the guard never fires on real data; divide unconditionally
-        // and select, with no branch around the division
-        const T v = div_nr(num, fmax(den, Tiny<T>::v));
-        return den >= Tiny<T>::v ? v : T(0);
-    } else {
-        // FP32: the guard fires wherever psi1 vanishes around the face (eps^3
-        // underflows), and waves lying wholly in such a region skip the
-        // division
-        return den >= Tiny<T>::v ? div_nr(num, den) : T(0);
-    }
-}
-
-// Limited pseudo-velocity; the factors are in limiter precision (double)
-// and already capped at 1 (min(1, a, b) = min(min(1, a), min(1, b)) exactly).
-template <typename T>
-__device__ __forceinline__ T limited(T v, double bup_a, double bdn_a, double bup_b, double bdn_b)
-{
-    const T cp = T(fmin(bdn_a, bup_b));
-    const T cn = T(fmin(bup_a, bdn_b));
-    return cp * pos(v) + cn * neg(v);
-}
-
-// Global memory is read and written through buffer descriptors: one
-// descriptor per plane of an array (base = the plane's first element, size =
-// the plane's bytes, built in scalar registers) and a loop-invariant 32-bit
-// byte offset per lane.  No 64-bit address arithmetic per access, and an
-// offset past the plane reads zero instead of leaving the array.  The host
-// keeps every plane below 4 GiB.
-using Rsrc = __amdgpu_buffer_rsrc_t;
-constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
-
-template <typename T> __device__ __forceinline__ Rsrc plane_rsrc(const T *base, size_t plane, unsigned plane_elems)
-{
-    return __builtin_amdgcn_make_buffer_rsrc((void *)(base + plane * plane_elems), 0,
-                                             (int)(plane_elems * (unsigned)sizeof(T)), kRsrcWord3);
-}
-
-// byte_off: per-lane offset; s_off: workgroup-uniform offset added to it
-template <typename T> __device__ __forceinline__ T bload(Rsrc r, unsigned byte_off, unsigned s_off = 0)
-{
-    if constexpr (sizeof(T) == 8)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, (int)s_off, 0));
-    else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, (int)s_off, 0));
-}
-
-template <typename T> __device__ __forceinline__ void bstore(Rsrc r, unsigned byte_off, T v)
-{
-    if constexpr (sizeof(T) == 8)
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
-                                              r, (int)byte_off, 0, 0);
-    else
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
-}
-
-// Lane exchange along x inside a wave.  A workgroup's rows are RX lanes long
-// and RX divides 64 or is 64, so the x-neighbours of a lane are the adjacent
-// lanes of its wave: from_lo(v) is v of lane i-1, from_hi(v) v of lane i+1
-// (DPP wave shifts).  The first and last lane of a row receive a value from
-// another row (or 0); they hold the outermost halo columns of the region,
-// and no output depends on what they compute from it.
-//
-// A DPP move reads its source from the other lanes only where those lanes
-// are active, so it must run with the full exec mask: every exchange is a
-// statement of its own in the uniform march (never an arm of a conditional
-// expression, which runs for the selected lanes only), and its result is
-// pinned there by an empty asm statement so that it is not sunk into a
-// lane-masked region either.
-constexpr int kDppWaveShr1 = 0x138, kDppWaveShl1 = 0x130;
-
-template <int CTRL> __device__ __forceinline__ float dpp(float v)
-{
-    float r = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
-    asm volatile("" : "+v"(r));
-    return r;
-}
-
-template <int CTRL> __device__ __forceinline__ double dpp(double v)
-{
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
-    double r = __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-    asm volatile("" : "+v"(r));
-    return r;
-}
-
-template <typename T> __device__ __forceinline__ T from_lo(T v) { return dpp<kDppWaveShr1>(v); }
-template <typename T> __device__ __forceinline__ T from_hi(T v) { return dpp<kDppWaveShl1>(v); }
-
-// Registers of one plane of a column: the Courant numbers of its x- and
-// y-faces and h (needed one iteration ahead) ...
-template <typename T> struct PlaneA {
-    T u1lo, u1hi, u2lo, u2hi, h;
-};
-// ... and psi^n and the Courant number of its lower z-face (needed two
-// iterations ahead).
-template <typename T> struct PlaneB {
-    T pn, u3lo;
-};
-
-// ================================================================ fused step
-
-// LDS planes of one workgroup (each padded by one cell on every side).
-template <typename T, int RX, int RY> struct Smem {
-    static constexpr int PX = RX + 2, PP = PX * (RY + 2);
-    T sP[PP];                            // psi^n plane t (its ring holds real data)
-    T sQ[3][PP];                         // psi1, planes t-2 .. t in fixed slots
-    T sC1[PP], sC2[PP], sC3[PP], sH[PP]; // Courant column sums, h: plane t-1
-    // x-face fluxes go through LDS only where x-neighbours are not
-    // exchanged between lanes (FP32)
-    static constexpr int PX1 = sizeof(T) == 8 ? 1 : PP;
-    T sFA1[PX1], sFA2[PP];               // antidiffusive donor fluxes, lower faces
-    double sBU[PP], sBD[PP];             // limiter factors, plane t-2
-    T sFC1[PX1], sFC2[PP];               // corrective fluxes, lower faces
-};
-
-// One workgroup advances the output tile (tx, ty) of grid g through planes
-// [z0, z1): psi[flip] -> psi[1 - flip].
-template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN>
-__device__ __forceinline__ void march(const GridDesc<T> &g, int flip, int tx, int ty, int z0,
-                                      int z1, double eps_d, Smem<T, RX, RY> &sm)
-{
-    using L = double;  // limiter precision (both variants)
-    constexpr int TX = RX - 4, TY = RY - 4;
-    constexpr int PX = RX + 2;           // padded row pitch of every LDS plane
-    constexpr int XM = -1, XP = 1, YM = -PX, YP = PX;
-    T *__restrict__ sP = sm.sP;
-    auto &sQ = sm.sQ;
-    T *__restrict__ sC1 = sm.sC1, *__restrict__ sC2 = sm.sC2, *__restrict__ sC3 = sm.sC3;
-    T *__restrict__ sH = sm.sH, *__restrict__ sFA1 = sm.sFA1, *__restrict__ sFA2 = sm.sFA2;
-    L *__restrict__ sBU = sm.sBU, *__restrict__ sBD = sm.sBD;
-    T *__restrict__ sFC1 = sm.sFC1, *__restrict__ sFC2 = sm.sFC2;
-
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const T eps = T(eps_d);
-    const L eps_l = eps_d;
-    const T *psi_in = g.psi[flip];
-    T *psi_out = g.psi[1 - flip];
-
-    const int tid = threadIdx.x;
-    const int lx = tid % RX, ly = tid / RX;
-    const int gx = tx * TX - 2 + lx;
-    const int gy = ty * TY - 2 + ly;
-    const int q = (ly + 1) * PX + lx + 1;
-
-    // in-plane offsets into the global arrays
-    const int cx = cell_of<OPEN>(gx, nx), cy = cell_of<OPEN>(gy, ny);
-    const unsigned pc_cells = (unsigned)nx * ny;
-    const unsigned pc_u1 = (unsigned)(nx + 1) * ny;
-    const unsigned pc_u2 = (unsigned)nx * (ny + 1);
-    const unsigned o_c = cy * nx + cx;
-    const unsigned o_u1lo = cy * (nx + 1) + face_lo<OPEN>(gx, nx);
-    const unsigned o_u1hi = cy * (nx + 1) + face_hi<OPEN>(gx, nx);
-    const unsigned o_u2lo = face_lo<OPEN>(gy, ny) * nx + cx;
-    const unsigned o_u2hi = face_hi<OPEN>(gy, ny) * nx + cx;
-    // The ring of the psi^n plane -- the padded LDS cells around the region,
-    // 2 RY of them left and right, 2 RX below and above -- is loaded by the
-    // first 2 (RX + RY) threads, one cell each (the other waves skip it).
-    constexpr int NRX = 2 * RY, NR = 2 * (RX + RY);
-    static_assert(NR <= RX * RY, "ring larger than the workgroup");
-    const bool has_ring = tid < NR;
-    int rgx = gx, rgy = gy, p_ring = q;
-    if (tid < NRX) {
-        const int side = tid / RY, row = tid % RY;
-        rgx = tx * TX - 2 + (side ? RX : -1);
-        rgy = ty * TY - 2 + row;
-        p_ring = (row + 1) * PX + (side ? RX + 1 : 0);
-    } else if (has_ring) {
-        const int side = (tid - NRX) / RX, col = (tid - NRX) % RX;
-        rgx = tx * TX - 2 + col;
-        rgy = ty * TY - 2 + (side ? RY : -1);
-        p_ring = (side ? RY + 1 : 0) * PX + col + 1;
-    }
-    const unsigned o_ring = cell_of<OPEN>(rgy, ny) * nx + cell_of<OPEN>(rgx, nx);
-    // byte offsets within a plane (the host keeps every plane below 4 GiB)
-    const unsigned b_c = o_c * (unsigned)sizeof(T);
-    const unsigned b_u1lo = o_u1lo * (unsigned)sizeof(T), b_u1hi = o_u1hi * (unsigned)sizeof(T);
-    const unsigned b_u2lo = o_u2lo * (unsigned)sizeof(T), b_u2hi = o_u2hi * (unsigned)sizeof(T);
-    const unsigned b_ring = o_ring * (unsigned)sizeof(T);
-
-    // cell-centred neighbour offsets: at an open boundary a read of the cell
-    // beyond it is redirected to the cell itself (zero gradient)
-    const bool edge_lo = OPEN && gx <= 0, edge_hi = OPEN && gx >= nx - 1;
-    const int cxm = edge_lo ? 0 : XM;
-    const int cxp = edge_hi ? 0 : XP;
-    const int cym = (OPEN && gy <= 0) ? 0 : YM;
-    const int cyp = (OPEN && gy >= ny - 1) ? 0 : YP;
-
-    // boundary-normal faces of an open domain carry no antidiffusive flux
-    const bool zero_v1 = OPEN && (gx <= 0 || gx >= nx);
-    const bool zero_v2 = OPEN && (gy <= 0 || gy >= ny);
-    const bool is_out = lx >= 2 && lx < RX - 2 && ly >= 2 && ly < RY - 2 && gx < nx && gy < ny;
-
-    // plane index of position t along z: wrapped (periodic) or clamped (open);
-    // the march advances it by one per iteration without a division
-    auto plane_of = [&](int t) { return cell_of<OPEN>(t, nz); };
-    auto zface_of = [&](int t) { return face_lo<OPEN>(t, nz); };
-    auto next_plane = [&](int k, int t_next) {
-        if (OPEN) return clampi(t_next, 0, nz - 1);
-        return k + 1 == nz ? 0 : k + 1;
-    };
-    auto load_a = [&](int k, PlaneA<T> &r) {
-        const Rsrc hp = plane_rsrc(g.h, k, pc_cells);
-        const Rsrc u1p = plane_rsrc(g.u1, k, pc_u1);
-        const Rsrc u2p = plane_rsrc(g.u2, k, pc_u2);
-        r.h = bload<T>(hp, b_c);
-        r.u1lo = bload<T>(u1p, b_u1lo);
-        if (OPEN) {
-            r.u1hi = bload<T>(u1p, b_u1hi);
-            r.u2lo = bload<T>(u2p, b_u2lo);
-            r.u2hi = bload<T>(u2p, b_u2hi);
-        } else {
-            // periodic: the upper faces are the next face along the axis and
-            // the lower y-face has the cell's own index, so no offsets of
-            // their own are held
-            r.u1hi = bload<T>(u1p, b_u1lo + (unsigned)sizeof(T));
-            r.u2lo = bload<T>(u2p, b_c);
-            r.u2hi = bload<T>(u2p, b_c, (unsigned)nx * (unsigned)sizeof(T));
-        }
-    };
-    auto load_b = [&](int k, int kf, PlaneB<T> &r) {
-        const Rsrc pp = plane_rsrc(psi_in, k, pc_cells);
-        const Rsrc u3p = plane_rsrc(g.u3, kf, pc_cells);
-        r.pn = bload<T>(pp, b_c);
-        r.u3lo = bload<T>(u3p, b_c);
-    };
-    // The ring threads load their ring cell of a plane late in the
-    // iteration before it is stored (it is not held across the heavy phase).
-    auto load_ring = [&](int k) {
-        return has_ring ? bload<T>(plane_rsrc(psi_in, k, pc_cells), b_ring) : T(0);
-    };
-
-    const int t0 = z0 - 2, tend = z1 + 2;
-    PlaneA<T> curA, nxA;
-    PlaneB<T> cur, nx1, nx2;
-    int ka = plane_of(t0 + 1);                     // plane of t+1 (load_a)
-    int kb = plane_of(t0 + 2);                     // plane of t+2 (load_b)
-    load_a(plane_of(t0), curA);
-    load_b(plane_of(t0), zface_of(t0), cur);
-    load_b(ka, zface_of(t0 + 1), nx1);
-    const T pn_prev = bload<T>(plane_rsrc(psi_in, plane_of(t0 - 1), pc_cells), b_c);
-    sP[q] = cur.pn;
-    if (has_ring) sP[p_ring] = load_ring(plane_of(t0));
-    T rng = load_ring(ka);  // ring cell of plane t+1
-
-    // z-history of the column
-    T f3_c = donor(pn_prev, cur.pn, cur.u3lo);  // psi^n flux, face t
-    T pn_m1 = pn_prev;
-    // max/min of psi^n over the in-plane 5-point stencil of plane t-1 and the
-    // plane below it: the bounds at t-1 add only psi^n(t) to these
-    T zmx_m1 = T(0), zmn_m1 = T(0);
-    T u1_m1 = T(0), u2_m1 = T(0);               // lower-face Courant, plane t-1
-    T rh_m1 = T(1), rh_m2 = T(1), rh_m3 = T(1); // 1/h of planes t-1 .. t-3
-    // Own-column psi1 of planes t-1 .. t-3 and the Courant sums and h of plane
-    // t-1 also sit in LDS (for the neighbours); the column keeps its own copy
-    // in registers.
-    // x-neighbours by lane exchange (FP64, where LDS bandwidth binds) or
-    // through LDS (FP32, where the exchange costs more issue than it saves)
-    constexpr bool kDpp = sizeof(T) == 8;
-    T r_p1_m1 = T(0), r_p1_m2 = T(0), r_p1_m3 = T(0);
-    T r_c1_m1 = T(0), r_c2_m1 = T(0), r_c3_m1 = T(0), r_h_m1 = T(0);
-    T v1_m2 = T(0), v2_m2 = T(0), v3_m1 = T(0); // V at plane t-2, V3 at face t-1
-    T fa3_m1 = T(0);                            // antidiffusive flux, face t-1
-    L bu_m2 = 1.0, bd_m2 = 1.0;                 // limiter factors (capped at 1), plane t-2
-    T fc3_m2 = T(0), fc3_m3 = T(0);             // corrective flux, faces t-2, t-3
-    T fc1_m3 = T(0), fc2_m3 = T(0);             // corrective fluxes, lower x/y faces of plane t-3
-
-    auto iter = [&](const int t, auto slot) {
-        constexpr int s0 = decltype(slot)::value;           // slot of plane t (held t-3)
-        constexpr int s1 = (s0 + 2) % 3, s2 = (s0 + 1) % 3; // planes t-1, t-2
-        load_a(ka, nxA);
-        load_b(kb, OPEN ? zface_of(t + 2) : kb, nx2);
-        ka = kb;
-        kb = next_plane(kb, t + 3);
-        __syncthreads();  // (B) psi^n(t), sums/h of t-1, corrective y-fluxes of t-3 are visible
-        // own-column values of planes t-1 .. t-3
-        const T p1_m1 = r_p1_m1, p1_m2 = r_p1_m2, p1_m3 = r_p1_m3;
-        const T c1_m1 = r_c1_m1, c2_m1 = r_c2_m1, c3_m1 = r_c3_m1, h_m1 = r_h_m1;
-
-        // limiter factors of plane t-2 (computed last iteration) for the
-        // neighbours' corrective pass after (F); their previous contents were
-        // last read before (B)
-        if (NONOS) {
-            sBU[q] = bu_m2;
-            sBD[q] = bd_m2;
-        }
-        {
-            // ---- S7 at plane t-3 (its corrective fluxes were stored last iteration)
-            T fc1hi;
-            if constexpr (kDpp) fc1hi = from_hi(fc1_m3);
-            else fc1hi = sFC1[q + XP];
-            const T fc2hi = sFC2[q + YP];
-            const T fc2lo = fc2_m3;
-            const T res = p1_m3 - (((fc1hi - fc1_m3) + (fc2hi - fc2lo)) + (fc3_m2 - fc3_m3)) * rh_m3;
-            if (is_out && t >= z0 + 3 && t <= tend)
-                bstore<T>(plane_rsrc<T>(psi_out, t - 3, pc_cells), b_c, res);
-        }
-
-        // ---- S1+S2 at plane t
-        const T pL = sP[q + cxm], pR = sP[q + cxp];
-        const T pD = sP[q + cym], pU = sP[q + cyp];
-        const T f1lo = donor(pL, cur.pn, curA.u1lo), f1hi = donor(cur.pn, pR, curA.u1hi);
-        const T f2lo = donor(pD, cur.pn, curA.u2lo), f2hi = donor(cur.pn, pU, curA.u2hi);
-        const T f3hi = donor(cur.pn, nx1.pn, nx1.u3lo);
-        const T rh_c = rcp_nr(curA.h);
-        const T p1_c = cur.pn - (((f1hi - f1lo) + (f2hi - f2lo)) + (f3hi - f3_c)) * rh_c;
-        // (at an open bottom the plane below t is t itself, already counted)
-        const bool zlo = OPEN && t <= 0;
-        const T zmx_c = fmax(fmax(fmax(pL, pR), fmax(pD, pU)), zlo ? cur.pn : fmax(cur.pn, pn_m1));
-        const T zmn_c = fmin(fmin(fmin(pL, pR), fmin(pD, pU)), zlo ? cur.pn : fmin(cur.pn, pn_m1));
-        sQ[s0][q] = p1_c;  // psi1(t-3) of this slot was last read before (B)
-        const T c1_c = curA.u1lo + curA.u1hi;
-        const T c2_c = curA.u2lo + curA.u2hi;
-        const T c3_c = cur.u3lo + nx1.u3lo;
-        __syncthreads();  // (D) psi1(t) and the limiter factors of t-2 are visible
-
-        T v1, v2, v3, fa1 = T(0), fa2 = T(0), fa3_c = T(0);
-        T pc_xlo = T(0), p2_xm = T(0);
-        T mx = T(0), mn = T(0);
-        {
-            // ---- S3 at plane p = t-1 (lower x- and y-faces) and on face t
-            const int p = t - 1;
-            const bool clo = OPEN && p <= 0, chi = OPEN && p >= nz - 1;
-            const T *Qc = sQ[s1];
-            const T *Qb = sQ[s0];
-            const T *Qlo = clo ? sQ[s1] : sQ[s2];
-            const T *Qhi = chi ? sQ[s1] : sQ[s0];
-            const T p1_lo = clo ? p1_m1 : p1_m2;
-            const T p1_hi = chi ? p1_m1 : p1_c;
-
-            // y-neighbours from LDS; x-neighbours from the adjacent lanes
-            // (FP64) or from LDS (FP32); at an open x-boundary the cell
-            // beyond is the cell itself
-            // ratio operands: |psi1| with the variable-sign option
-            auto av = [](T x) -> T {
-                if constexpr (VSIGN) return fabs(x);
-                else return x;
-            };
-            const T qd = Qc[q + YM];  // cell a of the lower y-face
-            const T qyp_ = Qc[q + cyp], qym_ = Qc[q + cym];
-            T qa, qxp_, qxm_;         // qa: cell a of the lower x-face
-            if constexpr (kDpp) {
-                qa = from_lo(p1_m1);
-                const T p1_xhi = from_hi(p1_m1);
-                qxp_ = edge_hi ? p1_m1 : p1_xhi;
-                qxm_ = edge_lo ? p1_m1 : qa;
-                // psi1 of t and t-2 of the lower x-neighbour (reused below)
-                pc_xlo = from_lo(p1_c);
-                p2_xm = from_lo(p1_m2);
-            } else {
-                qa = Qc[q + XM];
-                qxp_ = Qc[q + cxp];
-                qxm_ = Qc[q + cxm];
-            }
-            {
-                // x-face between a = (lx-1) and b = own; transverse axes y then z
-                T h_a, c2_a, c3_a, qyp_a, qym_a, phi_a, plo_a;
-                if constexpr (kDpp) {
-                    h_a = from_lo(h_m1), c2_a = from_lo(c2_m1), c3_a = from_lo(c3_m1);
-                    qyp_a = from_lo(qyp_), qym_a = from_lo(qym_);
-                    phi_a = chi ? qa : pc_xlo, plo_a = clo ? qa : p2_xm;
-                } else {
-                    h_a = sH[q + XM], c2_a = sC2[q + XM], c3_a = sC3[q + XM];
-                    qyp_a = Qc[q + XM + cyp], qym_a = Qc[q + XM + cym];
-                    phi_a = Qhi[q + XM], plo_a = Qlo[q + XM];
-                }
-                v1 = pseudo_velocity(u1_m1, h_a + h_m1, av(qa), av(p1_m1), c2_a + c2_m1,
-                                     av(qyp_) + av(qyp_a), av(qym_) + av(qym_a), c3_a + c3_m1,
-                                     av(p1_hi) + av(phi_a), av(p1_lo) + av(plo_a), eps);
-                if (zero_v1) v1 = T(0);
-            }
-            // the three faces are scheduled one after another: each face's
-            // temporaries die before the next face's reads are issued
-            __builtin_amdgcn_sched_barrier(0);
-            {
-                // y-face between a = (ly-1) and b = own; transverse axes z then x
-                T qd_xp, qd_xm;
-                if constexpr (kDpp) {
-                    const T xhi = from_hi(qd), xlo = from_lo(qd);
-                    qd_xp = edge_hi ? qd : xhi;
-                    qd_xm = edge_lo ? qd : xlo;
-                } else {
-                    qd_xp = Qc[q + YM + cxp];
-                    qd_xm = Qc[q + YM + cxm];
-                }
-                v2 = pseudo_velocity(u2_m1, sH[q + YM] + h_m1, av(qd), av(p1_m1),
-                                     sC3[q + YM] + c3_m1, av(p1_hi) + av(Qhi[q + YM]),
-                                     av(p1_lo) + av(Qlo[q + YM]), sC1[q + YM] + c1_m1,
-                                     av(qxp_) + av(qd_xp), av(qxm_) + av(qd_xm), eps);
-                if (zero_v2) v2 = T(0);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            {
-                // z-face t between a = plane t-1 and b = plane t; transverse x then y
-                T pc_xp, pc_xm;
-                if constexpr (kDpp) {
-                    const T xhi = from_hi(p1_c);
-                    pc_xp = edge_hi ? p1_c : xhi;
-                    pc_xm = edge_lo ? p1_c : pc_xlo;
-                } else {
-                    pc_xp = Qb[q + cxp];
-                    pc_xm = Qb[q + cxm];
-                }
-                v3 = pseudo_velocity(cur.u3lo, h_m1 + curA.h, av(p1_m1), av(p1_c), c1_m1 + c1_c,
-                                     av(pc_xp) + av(qxp_), av(pc_xm) + av(qxm_), c2_m1 + c2_c,
-                                     av(Qb[q + cyp]) + av(qyp_), av(Qb[q + cym]) + av(qym_), eps);
-            }
-            if (OPEN && (t <= 0 || t >= nz)) v3 = T(0);
-            if (NONOS) {
-                // ---- S4 bounds at plane p
-                // psi^n(t) is the plane above p (at an open top, p itself)
-                const T pn_hi = chi ? pn_m1 : cur.pn;
-                mx = fmax(fmax(fmax(zmx_m1, fmax(qxm_, qxp_)), fmax(fmax(qym_, qyp_), p1_m1)),
-                          fmax(pn_hi, fmax(p1_lo, p1_hi)));
-                mn = fmin(fmin(fmin(zmn_m1, fmin(qxm_, qxp_)), fmin(fmin(qym_, qyp_), p1_m1)),
-                          fmin(pn_hi, fmin(p1_lo, p1_hi)));
-                fa1 = donor(qa, p1_m1, v1);
-                fa2 = donor(qd, p1_m1, v2);
-                if constexpr (!kDpp) sFA1[q] = fa1;
-                sFA2[q] = fa2;
-                fa3_c = donor(p1_m1, p1_c, v3);
-            }
-        }
-        // psi^n of plane t+1: every read of plane t in sP happened before (D)
-        sP[q] = nx1.pn;
-        if (has_ring) sP[p_ring] = rng;
-        __syncthreads();  // (F) antidiffusive fluxes visible
-
-        L bu_m1 = 1.0, bd_m1 = 1.0;
-        if (NONOS) {
-            // ---- S5 limiter factors at plane t-1
-            T fa1_hi;
-            if constexpr (kDpp) fa1_hi = from_hi(fa1);
-            else fa1_hi = sFA1[q + XP];
-            const L x_lo = L(fa1), x_hi = L(fa1_hi);
-            const L y_lo = L(fa2), y_hi = L(sFA2[q + YP]);
-            const L z_lo = L(fa3_m1), z_hi = L(fa3_c);
-            const L in = ((pos(x_lo) - neg(x_hi)) + (pos(y_lo) - neg(y_hi))) + (pos(z_lo) - neg(z_hi));
-            const L ou = ((pos(x_hi) - neg(x_lo)) + (pos(y_hi) - neg(y_lo))) + (pos(z_hi) - neg(z_lo));
-            // beta_up = (mx - psi1) h / (IN + eps), beta_dn = (psi1 - mn) h / (OUT + eps),
-            // over the common denominator (IN + eps)(OUT + eps)
-            const L din = in + eps_l, dou = ou + eps_l;
-            const L r = rcp_nr(din * dou) * L(h_m1);
-            bu_m1 = fmin(L(1), ((L(mx) - L(p1_m1)) * dou) * r);
-            bd_m1 = fmin(L(1), ((L(p1_m1) - L(mn)) * din) * r);
-        }
-
-        T fc1_r, fc2_r, fc3_m1;
-        {
-            // ---- S6 + corrective fluxes at plane r = t-2 (lower faces) and on face t-1;
-            // the y-fluxes of t-3 in sFC2 were read before (D)
-            const T *Qr = sQ[s2];
-            T vt1 = v1_m2, vt2 = v2_m2, vt3 = v3_m1;
-            if (NONOS) {
-                L bu_a, bd_a;
-                if constexpr (kDpp) bu_a = from_lo(bu_m2), bd_a = from_lo(bd_m2);
-                else bu_a = sBU[q + XM], bd_a = sBD[q + XM];
-                vt1 = limited(v1_m2, bu_a, bd_a, bu_m2, bd_m2);
-                vt2 = limited(v2_m2, sBU[q + YM], sBD[q + YM], bu_m2, bd_m2);
-                vt3 = limited(v3_m1, bu_m2, bd_m2, bu_m1, bd_m1);
-            }
-            if (zero_v1) vt1 = T(0);
-            if (zero_v2) vt2 = T(0);
-            if (OPEN && (t - 1 <= 0 || t - 1 >= nz)) vt3 = T(0);
-            if constexpr (!kDpp) p2_xm = Qr[q + XM];
-            fc1_r = donor(p2_xm, p1_m2, vt1);
-            fc2_r = donor(Qr[q + YM], p1_m2, vt2);
-            if constexpr (!kDpp) sFC1[q] = fc1_r;
-            sFC2[q] = fc2_r;
-            fc3_m1 = donor(p1_m2, p1_m1, vt3);
-        }
-        // sums/h of plane t for the next iteration: the reads of plane t-1
-        // happened before (F)
-        sC1[q] = c1_c;
-        sC2[q] = c2_c;
-        sC3[q] = c3_c;
-        sH[q] = curA.h;
-        rng = load_ring(ka);  // plane t+2
-
-        // ---- hand the planes to the next iteration
-        pn_m1 = cur.pn;
-        zmx_m1 = zmx_c;
-        zmn_m1 = zmn_c;
-        u1_m1 = curA.u1lo;
-        u2_m1 = curA.u2lo;
-        rh_m3 = rh_m2;
-        rh_m2 = rh_m1;
-        rh_m1 = rh_c;
-        f3_c = f3hi;
-        v1_m2 = v1;
-        v2_m2 = v2;
-        v3_m1 = v3;
-        fa3_m1 = fa3_c;
-        bu_m2 = bu_m1;
-        bd_m2 = bd_m1;
-        fc3_m3 = fc3_m2;
-        fc3_m2 = fc3_m1;
-        fc1_m3 = fc1_r;
-        fc2_m3 = fc2_r;
-        {
-            r_p1_m3 = p1_m2;
-            r_p1_m2 = p1_m1;
-            r_p1_m1 = p1_c;
-            r_c1_m1 = c1_c;
-            r_c2_m1 = c2_c;
-            r_c3_m1 = c3_c;
-            r_h_m1 = curA.h;
-        }
-        curA = nxA;
-        cur = nx1;
-        nx1 = nx2;
-    };
-
-    // Unrolled by three so the psi1 planes sit in fixed slots (slot of plane
-    // t = (t - t0 + shift) mod 3); the iteration count modulo three is run
-    // first, in the last slots, so that no iteration is wasted.
-    int t = t0;
-    switch ((tend - t0 + 1) % 3) {
-    case 2:
-        iter(t++, std::integral_constant<int, 1>{});
-        [[fallthrough]];
-    case 1:
-        iter(t++, std::integral_constant<int, 2>{});
-        break;
-    default:
-        break;
-    }
-    for (; t <= tend; t += 3) {
-        iter(t, std::integral_constant<int, 0>{});
-        iter(t + 1, std::integral_constant<int, 1>{});
-        iter(t + 2, std::integral_constant<int, 2>{});
-    }
-}
 
 // Persistent step kernel: workgroup b walks the segments [wg_begin[b],
 // wg_begin[b+1]) of the plan -- (grid, tile, z-range) pieces balanced over
@@ -704,24 +21,14 @@ __global__ __launch_bounds__(RX * RY) void step_kernel(const GridDesc<T> *__rest
                                                       const int *__restrict__ wg_begin, int flip,
                                                       double eps, long long *__restrict__ seg_ticks)
 {
-    __shared__ Smem<T, RX, RY> sm;
-    // Every LDS plane starts at zero, so values computed from not-yet-written
-    // slots in the first iterations of a march stay finite (they never reach
-    // an output).
-    for (int i = threadIdx.x; i < Smem<T, RX, RY>::PP; i += RX * RY) {
-        sm.sP[i] = T(0);
-        sm.sQ[0][i] = sm.sQ[1][i] = sm.sQ[2][i] = T(0);
-        sm.sC1[i] = sm.sC2[i] = sm.sC3[i] = sm.sH[i] = T(0);
-        sm.sFA2[i] = sm.sFC2[i] = T(0);
-        if (i < Smem<T, RX, RY>::PX1) sm.sFA1[i] = sm.sFC1[i] = T(0);
-        sm.sBU[i] = sm.sBD[i] = 1.0;
-    }
-    __syncthreads();
+    __shared__ Smem<T, RX, RY, kModeStep> sm;
+    smem_clear(sm);
     const int b = wg_begin[blockIdx.x], e = wg_begin[blockIdx.x + 1];
     for (int s = b; s < e; ++s) {
         const Segment sg = segs[s];
         const long long t_start = seg_ticks ? (long long)wall_clock64() : 0;
-        march<T, RX, RY, OPEN, NONOS, VSIGN>(grids[sg.grid], flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+        march<T, RX, RY, OPEN, NONOS, VSIGN, kModeStep>(grids[sg.grid], PassIO<T>{}, flip, sg.tx,
+                                                        sg.ty, sg.z0, sg.z1, eps, sm);
         __syncthreads();
         // optional per-segment duration (workgroup-uniform; one lane stores)
         if (seg_ticks && threadIdx.x == 0) seg_ticks[s] = (long long)wall_clock64() - t_start;

@@ -65,7 +65,7 @@ def test_workspace_bytes():
 
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(nz=-1), dict(dtype=2), dict(bc=5),
-                                 dict(iord=3), dict(iord=1, nonos=1), dict(nonos=2),
+                                 dict(iord=0), dict(iord=17), dict(iord=1, nonos=1), dict(nonos=2),
                                  dict(eps=0.0), dict(eps=float("nan")), dict(tile=99),
                                  dict(nx=4096, ny=4096, nz=256),
                                  dict(nx=30000, ny=30000, nz=1)])
@@ -86,6 +86,25 @@ def test_vsign_flag_needs_a_default_launch_shape():
     for t in (1, 3, 4, 6):
         assert _lib.mpdata_workspace_bytes(_params(flags=vs, tile=t)) == 0
     assert _lib.mpdata_workspace_bytes(_params(flags=8)) == 0
+
+
+def test_more_corrective_passes_need_chain_buffers():
+    """iord > 2: one more iterate, the three velocity face arrays and (with
+    the limiter) the two running-bound arrays; a second set from iord 4 on;
+    only on the default launch shape."""
+    n, nf = 32 * 32 * 16, 33 * 32 * 16 + 32 * 33 * 16 + 32 * 32 * 17
+    b2 = _lib.mpdata_workspace_bytes(_params())
+    b3 = _lib.mpdata_workspace_bytes(_params(iord=3))
+    b4 = _lib.mpdata_workspace_bytes(_params(iord=4))
+    b16 = _lib.mpdata_workspace_bytes(_params(iord=16))
+    assert b3 - b2 >= (3 * n + nf) * 8
+    assert b4 - b3 >= (3 * n + nf) * 8
+    assert b16 > b4
+    assert _lib.mpdata_workspace_bytes(_params(iord=3, nonos=0)) <= b3 - 2 * n * 8
+    assert _lib.mpdata_workspace_bytes(_params(iord=3, tile=5)) == b3
+    assert _lib.mpdata_workspace_bytes(_params(iord=3, tile=1)) == 0
+    assert _lib.mpdata_workspace_bytes(_params(iord=3, dtype=1, bc=1, tile=2)) > 0
+    assert _lib.mpdata_workspace_bytes(_params(iord=3, dtype=1, bc=1, tile=5)) == 0
 
 
 def test_plane_limit_depends_on_word_size():
