@@ -2,8 +2,8 @@
 """Benchmark of the MPDATA time step on one MI355X.
 
 One "step" is one MPDATA time step (donor-cell pass, pseudo-velocities,
-limiter, corrective pass -- one launch of the fused kernel) over the whole
-grid.  The default workload is the 512x256x64 periodic solid-body-rotation
+limiter, corrective pass -- one launch of the fused kernel; with iord 3 a
+second corrective pass in a second launch) over the whole grid.  The default workload is the 512x256x64 periodic solid-body-rotation
 grid in FP64 (cone + slotted cube on a zero background, h in [0.8, 1.2]);
 inputs are synthetic, seeded and resident in HBM before the timed region.
 
@@ -35,6 +35,11 @@ WORKLOADS = {
                             "streamfunction 1024x512x64 open FP32 + FP64 limiter, limiter on, iord 2"),
     "streamfunction-fp64": ("streamfunction", "f64",
                             "streamfunction 1024x512x64 open FP64, limiter on, iord 2"),
+    "rotation-fp64-iord3": ("rotation", "f64",
+                            "rotation 512x256x64 periodic FP64, limiter on, iord 3 (two corrective "
+                            "passes: the fused step, then a second pass launch)"),
+    "rotation-fp32-iord3": ("rotation", "f32",
+                            "rotation 512x256x64 periodic FP32 + FP64 limiter, limiter on, iord 3"),
     "batched-fp32": ("batched", "f32",
                      "96 uneven periodic grids (nx, ny log-uniform in [32, 384], nz in [16, 64]), "
                      "FP32 + FP64 limiter, constant Courant per grid, one persistent launch per "
@@ -58,6 +63,26 @@ def algorithmic_bytes(shape, word):
     n = nx * ny * nz
     faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
     return word * (3 * n + faces)
+
+
+# corrective passes of a workload (iord), 2 unless named here
+IORD = {"rotation-fp64-iord3": 3, "rotation-fp32-iord3": 3}
+
+
+def chain_bytes(shape, word, iord, nonos=True):
+    """Bytes a step of iord > 2 moves by design: the fused step also writes
+    its limited velocity (3 face arrays) and, with the limiter, two running
+    bound arrays; each further pass reads its iterate, velocity, h and the
+    bounds, and writes the next iterate, velocity and bounds (the last pass
+    writes psi only)."""
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+    b = 2 if nonos else 0
+    head = 3 * n + faces + faces + b * n
+    mid = (2 + b) * n + faces + (1 + b) * n + faces
+    last = (2 + b) * n + faces + n
+    return word * (head + (iord - 3) * mid + last)
 
 
 PROFILES = {"rotation-fp64": "step_kernel_rotation_512x256x64_fp64.md",
@@ -94,14 +119,14 @@ def make_fields(kind):
     return inputs.rotation() if kind == "rotation" else inputs.streamfunction()
 
 
-def time_gpu(fields, dtype_tag, steps, warmup, tile=0):
+def time_gpu(fields, dtype_tag, steps, warmup, tile=0, iord=2):
     import numpy as np
     import torch
     from paper_1507_01265_amd.solver import Solver
 
     tdt = torch.float64 if dtype_tag == "f64" else torch.float32
     f = fields if dtype_tag == "f64" else fields.astype(np.float32)
-    s = Solver.from_numpy(f, dtype=tdt, device="cuda", tile=tile)
+    s = Solver.from_numpy(f, dtype=tdt, device="cuda", tile=tile, iord=iord)
     stream = s.stream
     m0 = s.mass()
     if warmup:
@@ -120,7 +145,7 @@ def time_gpu(fields, dtype_tag, steps, warmup, tile=0):
     return {"ms": ms, "mass0": m0, "mass1": m1, "psi_min": psi_min}
 
 
-def cpu_baseline(fields, budget_s=12.0, max_steps=40):
+def cpu_baseline(fields, budget_s=12.0, max_steps=40, iord=2):
     """The FP64 oracle as it stands, stepped on the host until the budget is
     spent (at least 2 steps)."""
     import oracle
@@ -129,7 +154,7 @@ def cpu_baseline(fields, budget_s=12.0, max_steps=40):
     steps = 0
     t0 = time.perf_counter()
     while True:
-        psi = oracle.step(psi, f.u1, f.u2, f.u3, f.h, bc=f.bc)
+        psi = oracle.step(psi, f.u1, f.u2, f.u3, f.h, bc=f.bc, iord=iord)
         steps += 1
         el = time.perf_counter() - t0
         if (steps >= 2 and el >= budget_s) or steps >= max_steps:
@@ -338,7 +363,8 @@ def main():
     word = 8 if dtag == "f64" else 4
 
     print(f"# timing {args.steps} steps after {args.warmup} warmup", file=sys.stderr, flush=True)
-    g = time_gpu(fields, dtag, args.steps, args.warmup, args.tile)
+    iord = IORD.get(args.workload, 2)
+    g = time_gpu(fields, dtag, args.steps, args.warmup, args.tile, iord)
     ms_per_step = g["ms"] / args.steps
     value = cells * args.steps / (g["ms"] / 1e3)
     abytes = algorithmic_bytes(fields.shape, word)
@@ -363,11 +389,15 @@ def main():
         "dtype": dtag,
         "data": "synthetic (seeded generator, resident in HBM)",
         "config": {"workload": desc, "nx": nx, "ny": ny, "nz": nz,
-                   "bc": "periodic" if fields.bc == 0 else "open", "iord": 2, "nonos": True,
+                   "bc": "periodic" if fields.bc == 0 else "open", "iord": iord, "nonos": True,
                    "tile": tile, "output_tile": f"{tx}x{ty}", "threads_per_workgroup": threads},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "algorithmic_bytes_per_launch": abytes},
+        **({"chain": {"launches_per_step": iord - 1,
+                      "bytes_per_step_by_design": chain_bytes(fields.shape, word, iord),
+                      "achieved_by_design_GBs": chain_bytes(fields.shape, word, iord)
+                      / (ms_per_step / 1e3) / 1e9}} if iord > 2 else {}),
         "mass_drift": (g["mass1"] - g["mass0"]) / g["mass0"],
         "psi_min": g["psi_min"],
     }
@@ -375,7 +405,7 @@ def main():
         import oracle
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         f64 = fields if dtag == "f64" else fields.astype("float32").as_f64()
-        steps, el = cpu_baseline(f64, args.cpu_budget)
+        steps, el = cpu_baseline(f64, args.cpu_budget, iord=iord)
         line["cpu_baseline"] = {"value": cells * steps / el, "unit": "cell-updates/s",
                                 "cores": oracle.threads(), "kind": "oracle",
                                 "sample": f"{nx}x{ny}x{nz} {args.workload} inputs, {steps} FP64 "

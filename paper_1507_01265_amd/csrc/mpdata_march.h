@@ -252,15 +252,15 @@ template <typename T> __device__ __forceinline__ T from_lo(T v) { return dpp<kDp
 template <typename T> __device__ __forceinline__ T from_hi(T v) { return dpp<kDppWaveShl1>(v); }
 
 // Registers of one plane of a column: the Courant numbers of its x- and
-// y-faces and h (needed one iteration ahead; in a further corrective pass
-// also the running bounds bx, bn of the earlier iterates) ...
+// y-faces and h (needed one iteration ahead) ...
 template <typename T> struct PlaneA {
-    T u1lo, u1hi, u2lo, u2hi, h, bx, bn;
+    T u1lo, u1hi, u2lo, u2hi, h;
 };
 // ... and psi^n and the Courant number of its lower z-face (needed two
-// iterations ahead).
+// iterations ahead; in a further corrective pass also the running bounds
+// bx, bn of the earlier iterates).
 template <typename T> struct PlaneB {
-    T pn, u3lo;
+    T pn, u3lo, bx, bn;
 };
 
 // ================================================================ fused step
@@ -411,16 +411,16 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             r.u2lo = bload<T>(u2p, b_c);
             r.u2hi = bload<T>(u2p, b_c, (unsigned)nx * (unsigned)sizeof(T));
         }
-        if constexpr (kPass && NONOS) {
-            r.bx = bload<T>(plane_rsrc(io.bmx, k, pc_cells), b_c);
-            r.bn = bload<T>(plane_rsrc(io.bmn, k, pc_cells), b_c);
-        }
     };
     auto load_b = [&](int k, int kf, PlaneB<T> &r) {
         const Rsrc pp = plane_rsrc(psi_in, k, pc_cells);
         const Rsrc u3p = plane_rsrc(g.u3, kf, pc_cells);
         r.pn = bload<T>(pp, b_c);
         r.u3lo = bload<T>(u3p, b_c);
+        if constexpr (kPass && NONOS) {
+            r.bx = bload<T>(plane_rsrc(io.bmx, k, pc_cells), b_c);
+            r.bn = bload<T>(plane_rsrc(io.bmn, k, pc_cells), b_c);
+        }
     };
     // The ring threads load their ring cell of a plane late in the
     // iteration before it is stored (it is not held across the heavy phase).
@@ -444,8 +444,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         const int kp = plane_of(t0 - 1);
         M_m1 = fmax(bload<T>(plane_rsrc(io.bmx, kp, pc_cells), b_c), pn_prev);
         m_m1 = fmin(bload<T>(plane_rsrc(io.bmn, kp, pc_cells), b_c), pn_prev);
-        M_c = fmax(curA.bx, cur.pn);
-        m_c = fmin(curA.bn, cur.pn);
+        M_c = fmax(cur.bx, cur.pn);
+        m_c = fmin(cur.bn, cur.pn);
         sP[q] = M_c;
         sPm[q] = m_c;
     } else if constexpr (!kPass) {
@@ -733,7 +733,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         if constexpr (kPass && NONOS) {
             // running bounds of plane t+1 for the next iteration's stencil;
             // every read of sP/sPm of plane t happened before (D)
-            const T M_n = fmax(nxA.bx, nx1.pn), m_n = fmin(nxA.bn, nx1.pn);
+            const T M_n = fmax(nx1.bx, nx1.pn), m_n = fmin(nx1.bn, nx1.pn);
             sP[q] = M_n;
             sPm[q] = m_n;
             M_m1 = M_c;
