@@ -36,6 +36,7 @@ class _Params(ctypes.Structure):
         ("iord", ctypes.c_int),
         ("nonos", ctypes.c_int),
         ("vsign", ctypes.c_int),
+        ("div", ctypes.c_int),
         ("eps", ctypes.c_double),
     ]
 
@@ -92,9 +93,10 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _params(shape, bc, iord, nonos, eps, vsign=False):
+def _params(shape, bc, iord, nonos, eps, vsign=False, div=False):
     nz, ny, nx = shape
-    return _Params(nx, ny, nz, int(bc), int(iord), int(bool(nonos)), int(bool(vsign)), float(eps))
+    return _Params(nx, ny, nz, int(bc), int(iord), int(bool(nonos)), int(bool(vsign)),
+                   int(bool(div)), float(eps))
 
 
 def _inputs(psi, u1, u2, u3, h):
@@ -108,11 +110,12 @@ def _inputs(psi, u1, u2, u3, h):
 
 
 def step(psi, u1, u2, u3, h, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15,
-         stages=False, vsign=False):
+         stages=False, vsign=False, div=False):
     """One step; returns psi at n+1 (and a dict of stage arrays if asked).
-    vsign: the variable-sign option (|psi1| in the pseudo-velocity ratios)."""
+    vsign: the variable-sign option (|psi1| in the pseudo-velocity ratios);
+    div: the divergent-flow term of the pseudo-velocity."""
     psi, u1, u2, u3, h = _inputs(psi, u1, u2, u3, h)
-    p = _params(psi.shape, bc, iord, nonos, eps, vsign)
+    p = _params(psi.shape, bc, iord, nonos, eps, vsign, div)
     out = np.empty_like(psi)
     st = None
     arrays = {}
@@ -132,11 +135,11 @@ def step(psi, u1, u2, u3, h, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15,
 
 
 def run(psi, u1, u2, u3, h, nsteps, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15,
-        vsign=False):
+        vsign=False, div=False):
     """nsteps steps; returns a new array."""
     psi, u1, u2, u3, h = _inputs(psi, u1, u2, u3, h)
     psi = psi.copy()
-    p = _params(psi.shape, bc, iord, nonos, eps, vsign)
+    p = _params(psi.shape, bc, iord, nonos, eps, vsign, div)
     rc = _load().orc_run(ctypes.byref(p), _ptr(psi), _ptr(u1), _ptr(u2), _ptr(u3),
                          _ptr(h), int(nsteps))
     if rc:

@@ -52,6 +52,18 @@
  * the (limited) antidiffusive velocity of pass k-1 in the place of the
  * Courant numbers; h, eps and the options are the same in every pass.
  *
+ * Option div (flows that are not divergence-free, Smolarkiewicz 1984; the
+ * density-weighted form of Smolarkiewicz & Margolin 1998): the donor-cell
+ * pass of a divergent flow leaves a first-order error proportional to psi
+ * times the divergence, which the pseudo-velocity takes back with the term
+ *   -(1/4) (U/G) dv
+ * on every face, dv the centred divergence of the pass's velocity field
+ * across the face: along the face's own axis the difference of the faces
+ * beyond b and below a, along each transverse axis the upper faces of a and
+ * b minus their lower faces (own axis, then the transverse axes in the
+ * cyclic order).  In a later pass the velocity field is the previous pass's
+ * antidiffusive velocity, which is divergent in general.
+ *
  * Layout: cell arrays are [k][j][i] with i fastest, nx*ny*nz doubles.
  * Face arrays hold n+1 faces along their own axis: u1[k][j][i'] with
  * i' = 0..nx (face i' lies between cells i'-1 and i'), u2[k][j'][i],
@@ -176,7 +188,8 @@ static double pseudo_velocity(double U, double G, double pa, double pb,
                               double us_a, double us_b, double ps_a_hi, double ps_b_hi,
                               double ps_a_lo, double ps_b_lo,
                               double ut_a, double ut_b, double pt_a_hi, double pt_b_hi,
-                              double pt_a_lo, double pt_b_lo, double eps)
+                              double pt_a_lo, double pt_b_lo, double eps, int div,
+                              double dv)
 {
     double A = (pb - pa) / (pb + pa + eps);
     double Us = 0.25 * (us_a + us_b);
@@ -185,14 +198,29 @@ static double pseudo_velocity(double U, double G, double pa, double pb,
     double Ut = 0.25 * (ut_a + ut_b);
     double t_hi = pt_b_hi + pt_a_hi, t_lo = pt_b_lo + pt_a_lo;
     double Bt = 0.5 * (t_hi - t_lo) / (t_hi + t_lo + eps);
-    return (fabs(U) - U * U / G) * A - (U / G) * (Us * Bs + Ut * Bt);
+    double V = (fabs(U) - U * U / G) * A - (U / G) * (Us * Bs + Ut * Bt);
+    if (div) V = V - 0.25 * (U / G) * dv;
+    return V;
+}
+
+/* Face index f along an axis of n cells, for the neighbouring faces the
+ * divergence estimate reads: periodic wraps (face n is face 0), open clamps
+ * (only boundary-normal faces, whose V is zero anyway, reach past the ends). */
+static int fres(int f, int n, int bc)
+{
+    if (bc == ORC_BC_PERIODIC) {
+        f %= n;
+        return f < 0 ? f + n : f;
+    }
+    return f < 0 ? 0 : (f > n ? n : f);
 }
 
 static void pseudo_velocities(const grid *g, const double *p, const double *u1,
                               const double *u2, const double *u3, const double *h,
-                              double eps, double *v1, double *v2, double *v3)
+                              double eps, int div, double *v1, double *v2, double *v3)
 {
     const int open = g->bc == ORC_BC_OPEN;
+    const int bc = g->bc;
     int k;
 #pragma omp parallel for schedule(static)
     for (k = 0; k < g->nz; ++k)
@@ -206,13 +234,21 @@ static void pseudo_velocities(const grid *g, const double *p, const double *u1,
                 double sb2 = u2[yface(g, b, j, k)] + u2[yface(g, b, j + 1, k)];
                 double sa3 = u3[zface(g, a, j, k)] + u3[zface(g, a, j, k + 1)];
                 double sb3 = u3[zface(g, b, j, k)] + u3[zface(g, b, j, k + 1)];
+                double dv = 0.0;
+                if (div)
+                    dv = ((u1[xface(g, fres(f + 1, g->nx, bc), j, k)] -
+                           u1[xface(g, fres(f - 1, g->nx, bc), j, k)]) +
+                          ((u2[yface(g, a, j + 1, k)] + u2[yface(g, b, j + 1, k)]) -
+                           (u2[yface(g, a, j, k)] + u2[yface(g, b, j, k)]))) +
+                         ((u3[zface(g, a, j, k + 1)] + u3[zface(g, b, j, k + 1)]) -
+                          (u3[zface(g, a, j, k)] + u3[zface(g, b, j, k)]));
                 v1[o] = pseudo_velocity(
                     u1[o], 0.5 * (h[cell(g, a, j, k)] + h[cell(g, b, j, k)]),
                     p[cell(g, a, j, k)], p[cell(g, b, j, k)],
                     sa2, sb2, p[cell(g, a, j + 1, k)], p[cell(g, b, j + 1, k)],
                     p[cell(g, a, j - 1, k)], p[cell(g, b, j - 1, k)],
                     sa3, sb3, p[cell(g, a, j, k + 1)], p[cell(g, b, j, k + 1)],
-                    p[cell(g, a, j, k - 1)], p[cell(g, b, j, k - 1)], eps);
+                    p[cell(g, a, j, k - 1)], p[cell(g, b, j, k - 1)], eps, div, dv);
             }
 #pragma omp parallel for schedule(static)
     for (k = 0; k < g->nz; ++k)
@@ -226,13 +262,21 @@ static void pseudo_velocities(const grid *g, const double *p, const double *u1,
                 double sb3 = u3[zface(g, i, b, k)] + u3[zface(g, i, b, k + 1)];
                 double sa1 = u1[xface(g, i, a, k)] + u1[xface(g, i + 1, a, k)];
                 double sb1 = u1[xface(g, i, b, k)] + u1[xface(g, i + 1, b, k)];
+                double dv = 0.0;
+                if (div)
+                    dv = ((u2[yface(g, i, fres(f + 1, g->ny, bc), k)] -
+                           u2[yface(g, i, fres(f - 1, g->ny, bc), k)]) +
+                          ((u3[zface(g, i, a, k + 1)] + u3[zface(g, i, b, k + 1)]) -
+                           (u3[zface(g, i, a, k)] + u3[zface(g, i, b, k)]))) +
+                         ((u1[xface(g, i + 1, a, k)] + u1[xface(g, i + 1, b, k)]) -
+                          (u1[xface(g, i, a, k)] + u1[xface(g, i, b, k)]));
                 v2[o] = pseudo_velocity(
                     u2[o], 0.5 * (h[cell(g, i, a, k)] + h[cell(g, i, b, k)]),
                     p[cell(g, i, a, k)], p[cell(g, i, b, k)],
                     sa3, sb3, p[cell(g, i, a, k + 1)], p[cell(g, i, b, k + 1)],
                     p[cell(g, i, a, k - 1)], p[cell(g, i, b, k - 1)],
                     sa1, sb1, p[cell(g, i + 1, a, k)], p[cell(g, i + 1, b, k)],
-                    p[cell(g, i - 1, a, k)], p[cell(g, i - 1, b, k)], eps);
+                    p[cell(g, i - 1, a, k)], p[cell(g, i - 1, b, k)], eps, div, dv);
             }
     int f;
 #pragma omp parallel for schedule(static)
@@ -247,13 +291,21 @@ static void pseudo_velocities(const grid *g, const double *p, const double *u1,
                 double sb1 = u1[xface(g, i, j, b)] + u1[xface(g, i + 1, j, b)];
                 double sa2 = u2[yface(g, i, j, a)] + u2[yface(g, i, j + 1, a)];
                 double sb2 = u2[yface(g, i, j, b)] + u2[yface(g, i, j + 1, b)];
+                double dv = 0.0;
+                if (div)
+                    dv = ((u3[zface(g, i, j, fres(f + 1, g->nz, bc))] -
+                           u3[zface(g, i, j, fres(f - 1, g->nz, bc))]) +
+                          ((u1[xface(g, i + 1, j, a)] + u1[xface(g, i + 1, j, b)]) -
+                           (u1[xface(g, i, j, a)] + u1[xface(g, i, j, b)]))) +
+                         ((u2[yface(g, i, j + 1, a)] + u2[yface(g, i, j + 1, b)]) -
+                          (u2[yface(g, i, j, a)] + u2[yface(g, i, j, b)]));
                 v3[o] = pseudo_velocity(
                     u3[o], 0.5 * (h[cell(g, i, j, a)] + h[cell(g, i, j, b)]),
                     p[cell(g, i, j, a)], p[cell(g, i, j, b)],
                     sa1, sb1, p[cell(g, i + 1, j, a)], p[cell(g, i + 1, j, b)],
                     p[cell(g, i - 1, j, a)], p[cell(g, i - 1, j, b)],
                     sa2, sb2, p[cell(g, i, j + 1, a)], p[cell(g, i, j + 1, b)],
-                    p[cell(g, i, j - 1, a)], p[cell(g, i, j - 1, b)], eps);
+                    p[cell(g, i, j - 1, a)], p[cell(g, i, j - 1, b)], eps, div, dv);
             }
 }
 
@@ -376,6 +428,7 @@ int orc_check(const orc_params *p)
     if (p->iord < 1 || p->iord > ORC_MAX_IORD) return -1;
     if (p->nonos != 0 && p->nonos != 1) return -1;
     if (p->vsign != 0 && p->vsign != 1) return -1;
+    if (p->div != 0 && p->div != 1) return -1;
     if (!(p->eps > 0.0)) return -1;
     return 0;
 }
@@ -428,9 +481,9 @@ int orc_step(const orc_params *p, const double *psi, const double *u1,
         if (p->vsign) {
             /* S3 on |psi^(k)| (option vsign); the limiter and S7 keep psi^(k) */
             for (long c = 0; c < n; ++c) a1[c] = fabs(cur[c]);
-            pseudo_velocities(&g, a1, c1, c2, c3, h, p->eps, v[0], v[1], v[2]);
+            pseudo_velocities(&g, a1, c1, c2, c3, h, p->eps, p->div, v[0], v[1], v[2]);
         } else {
-            pseudo_velocities(&g, cur, c1, c2, c3, h, p->eps, v[0], v[1], v[2]);   /* S3 */
+            pseudo_velocities(&g, cur, c1, c2, c3, h, p->eps, p->div, v[0], v[1], v[2]); /* S3 */
         }
         const int last = k == npass;
         if (last && st && st->v1) memcpy(st->v1, v[0], sizeof(double) * n1);

@@ -20,6 +20,7 @@ typedef struct {
     int iord;       /* 1: donor cell only; k > 1: k - 1 corrective passes */
     int nonos;      /* 1: non-oscillatory limiter on */
     int vsign;      /* 1: fields of variable sign -- |psi1| in the ratios A, B */
+    int div;        /* 1: divergent-flow term in the pseudo-velocity */
     double eps;     /* regulariser of ratio denominators */
 } orc_params;
 

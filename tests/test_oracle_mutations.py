@@ -17,11 +17,11 @@ import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "mpdata_oracle.c")
 
-PV = "return (fabs(U) - U * U / G) * A - (U / G) * (Us * Bs + Ut * Bt);"
+PV = "double V = (fabs(U) - U * U / G) * A - (U / G) * (Us * Bs + Ut * Bt);"
 MUTANTS = {
-    "drop_cross_terms": (PV, "return (fabs(U) - U * U / G) * A;"),
-    "no_face_density": (PV, "return (fabs(U) - U * U) * A - U * (Us * Bs + Ut * Bt);"),
-    "cross_term_sign": (PV, "return (fabs(U) - U * U / G) * A + (U / G) * (Us * Bs + Ut * Bt);"),
+    "drop_cross_terms": (PV, "double V = (fabs(U) - U * U / G) * A;"),
+    "no_face_density": (PV, "double V = (fabs(U) - U * U) * A - U * (Us * Bs + Ut * Bt);"),
+    "cross_term_sign": (PV, "double V = (fabs(U) - U * U / G) * A + (U / G) * (Us * Bs + Ut * Bt);"),
     "cross_term_factor": ("double Bs = 0.5 * (s_hi - s_lo)", "double Bs = (s_hi - s_lo)"),
     "transposed_A": ("double A = (pb - pa) / (pb + pa + eps);",
                      "double A = (pa - pb) / (pb + pa + eps);"),
@@ -42,6 +42,13 @@ MUTANTS = {
     "later_pass_keeps_courant": ("        c1 = v[0];\n        c2 = v[1];\n        c3 = v[2];\n", ""),
     "bounds_not_cumulative": ("bounds(&g, it, k + 1, mx, mn);",
                               "const double *two[2] = {psi, cur};\n            bounds(&g, two, 2, mx, mn);"),
+    "div_term_sign": ("if (div) V = V - 0.25 * (U / G) * dv;", "if (div) V = V + 0.25 * (U / G) * dv;"),
+    "div_term_factor": ("if (div) V = V - 0.25 * (U / G) * dv;", "if (div) V = V - 0.5 * (U / G) * dv;"),
+    "div_x_face_own_axis_only": (
+        """                    dv = ((u1[xface(g, fres(f + 1, g->nx, bc), j, k)] -
+                           u1[xface(g, fres(f - 1, g->nx, bc), j, k)]) +""",
+        """                    dv = ((u1[xface(g, fres(f + 1, g->nx, bc), j, k)] -
+                           u1[xface(g, fres(f - 1, g->nx, bc), j, k)]) + 0.0 * """),
     "vsign_in_corrective_pass": ("donor_cell_pass(&g, cur, v[0], v[1], v[2], h, own[k + 1]);",
                                  "donor_cell_pass(&g, p->vsign ? a1 : cur, v[0], v[1], v[2], h, own[k + 1]);"),
 }
@@ -67,6 +74,9 @@ def _checks():
     out["vsign_wave"] = lambda: pins.test_vsign_advects_a_sign_changing_wave(oracle)
     out["iord3_bounds"] = lambda: pins.test_more_passes_bound_over_every_iterate(oracle)
     out["iord3_error_1d"] = lambda: pins.test_a_second_pass_reduces_the_error_1d(oracle, 0.0)
+    out["div_hand"] = lambda: pins.test_divergence_term_by_hand(oracle)
+    out["div_order_1d"] = lambda: pins.test_divergence_term_restores_second_order_1d(oracle, 2)
+    out["div_2d"] = lambda: pins.test_divergence_term_transverse_parts_2d(oracle)
     return out
 
 
@@ -102,11 +112,13 @@ def test_mutant_is_caught(name, tmp_path):
     failed = []
     try:
         oracle._lib, oracle._LIB = None, str(lib)
+        # checks run cheapest first; one failing check is enough
         for cname, fn in _checks().items():
             try:
                 fn()
             except (AssertionError, ValueError):
                 failed.append(cname)
+                break
     finally:
         oracle._lib, oracle._LIB = saved_lib, saved_path
     assert failed, f"mutant {name} passed every pin"

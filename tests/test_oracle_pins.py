@@ -529,3 +529,113 @@ def test_more_passes_bound_over_every_iterate(orc):
     np.testing.assert_array_equal(st["mn"], brute(fields, np.min))
     assert ((brute([f.psi, p2], np.max) != st["mx"]).any() or
             (brute([f.psi, p2], np.min) != st["mn"]).any())
+
+
+# ------------------------------------------------- divergent-flow term (div)
+
+def test_divergence_term_by_hand(orc):
+    """4-cell line with uneven face Courant numbers: V and the step with and
+    without the term against exact rationals (tests/golden/hand_div_1d.json)."""
+    g = json.load(open(os.path.join(GOLDEN, "hand_div_1d.json")))
+    psi = _fr(g["psi0"]).reshape(1, 1, 4)
+    u1 = _fr(g["u1_faces_0_to_4"]).reshape(1, 1, 5)
+    args = (psi, u1, np.zeros((1, 2, 4)), np.zeros((2, 1, 4)), np.ones((1, 1, 4)))
+    for key, div in (("without_term", False), ("with_term", True)):
+        out, st = orc.step(*args, nonos=False, stages=True, div=div)
+        np.testing.assert_allclose(st["psi1"].ravel(), _fr(g["psi1"]), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(st["v1"].ravel(), _fr(g[key]["v1_faces_0_to_4"]), rtol=0,
+                                   atol=1e-14)
+        np.testing.assert_allclose(out.ravel(), _fr(g[key]["psi"]), rtol=0, atol=1e-14)
+
+
+def _rk4_back(x, vel, T, nsub=2000):
+    """Foot of the characteristic dx/dt = vel(x) through x after time T."""
+    dt = T / nsub
+    for _ in range(nsub):
+        k1 = -vel(x)
+        k2 = -vel(x + 0.5 * dt * k1)
+        k3 = -vel(x + 0.5 * dt * k2)
+        k4 = -vel(x + dt * k3)
+        x = x + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return x
+
+
+def _divergent_1d_errors(orc, div, sizes, iord=2, C0=0.3, amp=0.5):
+    """d psi/dt + d(u psi)/dx = 0 with steady u(x) = C0 (1 + amp sin(2 pi x/N)):
+    u psi is constant along dx/dt = u, so psi(x, T) = psi0(X) u(X) / u(x) with
+    X the foot of the characteristic (integrated by RK4 to 1e-12)."""
+    errs = []
+    for N in sizes:
+        vel = lambda x: C0 * (1 + amp * np.sin(2 * np.pi * x / N))
+        f = np.arange(N + 1, dtype=float)
+        U = vel(f)
+        U[-1] = U[0]
+        x = np.arange(N) + 0.5
+        psi0 = lambda X: 2 + np.sin(2 * np.pi * X / N)
+        steps = int(round(N / 4 / C0))
+        out = orc.run(psi0(x).reshape(1, 1, N), U.reshape(1, 1, N + 1), np.zeros((1, 2, N)),
+                      np.zeros((2, 1, N)), np.ones((1, 1, N)), steps, iord=iord, nonos=False,
+                      div=div)
+        X = _rk4_back(x, vel, steps)
+        errs.append(np.abs(out.ravel() - psi0(X) * vel(X) / vel(x)).max())
+    return np.array(errs)
+
+
+@pytest.mark.parametrize("iord", [2, 3])
+def test_divergence_term_restores_second_order_1d(orc, iord):
+    """In a divergent flow the donor-cell error has a part proportional to
+    psi times the divergence; without the term MPDATA is only first order
+    there, with it second order."""
+    e_on = _divergent_1d_errors(orc, True, (64, 128, 256), iord)
+    e_off = _divergent_1d_errors(orc, False, (64, 128, 256), iord)
+    assert np.all(e_on[:-1] / e_on[1:] > 3.5), e_on[:-1] / e_on[1:]
+    assert np.all(e_off[:-1] / e_off[1:] < 2.4), e_off[:-1] / e_off[1:]
+    assert e_on[-1] < 0.15 * e_off[-1]
+
+
+def test_divergence_term_transverse_parts_2d(orc):
+    """Separable divergent flow u(x), v(y): psi u(x) v(y) is constant along the
+    characteristics.  Second order needs the transverse parts of the
+    divergence across each face."""
+    def err(N, div):
+        c1, c2, amp = 0.25, 0.2, 0.4
+        ux = lambda x: c1 * (1 + amp * np.sin(2 * np.pi * x / N))
+        vy = lambda y: c2 * (1 + amp * np.cos(2 * np.pi * y / N))
+        f = np.arange(N + 1, dtype=float)
+        cc = np.arange(N) + 0.5
+        U1 = np.broadcast_to(ux(f)[None, None, :], (1, N, N + 1)).copy()
+        U1[..., -1] = U1[..., 0]
+        U2 = np.broadcast_to(vy(f)[None, :, None], (1, N + 1, N)).copy()
+        U2[:, -1, :] = U2[:, 0, :]
+        prof = lambda X, Y: 2 + np.sin(2 * np.pi * X / N) * np.cos(2 * np.pi * Y / N)
+        Y, X = np.meshgrid(cc, cc, indexing="ij")
+        steps = int(round(N / 4 / 0.3))
+        out = orc.run(prof(X, Y)[None], U1, U2, np.zeros((2, N, N)), np.ones((1, N, N)), steps,
+                      nonos=False, div=div)
+        Y0, X0 = np.meshgrid(_rk4_back(cc, vy, steps), _rk4_back(cc, ux, steps), indexing="ij")
+        exact = prof(X0, Y0) * ux(X0) * vy(Y0) / (ux(X) * vy(Y))
+        return np.abs(out[0] - exact).max()
+    e = [err(N, True) for N in (128, 256)]
+    assert e[0] / e[1] > 3.7, e
+    assert e[1] < 0.1 * err(256, False)
+
+
+@pytest.mark.parametrize("kind,bc", [("constant", 0), ("rotation", 0), ("streamfunction", 1)])
+def test_divergence_term_vanishes_on_solenoidal_flows(orc, kind, bc):
+    """Constant, solid-body and quantised-streamfunction Courant numbers have
+    an exactly zero discrete divergence, so the term adds exact zeros."""
+    shape = (8, 12, 16)
+    u1, u2, u3, h = _fields_for_constant(kind, shape, bc)
+    psi = inputs.random_smooth(23, shape).psi
+    a = orc.run(psi, u1, u2, u3, h, 3, bc=bc)
+    b = orc.run(psi, u1, u2, u3, h, 3, bc=bc, div=True)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_divergence_term_conserves_mass(orc):
+    shape = (8, 12, 16)
+    f = inputs.random_smooth(24, shape, cmax=0.15)  # random faces: divergent
+    m0 = orc.mass(f.psi, f.h)
+    out = orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 5, div=True, iord=3)
+    assert abs(orc.mass(out, f.h) - m0) / m0 < 1e-13
+    assert not np.array_equal(out, orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 5, iord=3))
