@@ -66,9 +66,13 @@ enum { MPDATA_FP64 = 0, MPDATA_FP32 = 1 };
  * captured graph of step launches.  VSIGN -- fields of variable sign: the
  * ratios of the antidiffusive pseudo-velocity take |psi1| in place of psi1
  * (the variable-sign option of the MPDATA literature the paper cites,
- * Smolarkiewicz & Margolin 1998); built for the default launch shapes
- * (tile 0, 2 or 5). */
-enum { MPDATA_FLAG_NO_GRAPH = 1, MPDATA_FLAG_VSIGN = 2 };
+ * Smolarkiewicz & Margolin 1998).  DIV -- flows that are not divergence-free:
+ * the pseudo-velocity gains the divergent-flow term -(1/4)(U/G) dv, dv the
+ * centred divergence of the pass's velocity field across the face
+ * (Smolarkiewicz 1984); on a discretely divergence-free flow it adds exact
+ * zeros.  VSIGN and DIV are built for the default launch shapes (tile 0, 2
+ * or 5). */
+enum { MPDATA_FLAG_NO_GRAPH = 1, MPDATA_FLAG_VSIGN = 2, MPDATA_FLAG_DIV = 4 };
 enum { MPDATA_BC_PERIODIC = 0, MPDATA_BC_OPEN = 1 }; /* OPEN = zero gradient */
 
 typedef struct {

@@ -26,6 +26,7 @@ MPDATA_BC_PERIODIC = 0
 MPDATA_BC_OPEN = 1
 MPDATA_FLAG_NO_GRAPH = 1
 MPDATA_FLAG_VSIGN = 2
+MPDATA_FLAG_DIV = 4
 
 ERRORS = {MPDATA_EINVAL: "EINVAL", MPDATA_ENOMEM: "ENOMEM", MPDATA_EDEVICE: "EDEVICE",
           MPDATA_ENOTSUP: "ENOTSUP", MPDATA_ENONFINITE: "ENONFINITE"}

@@ -76,16 +76,18 @@ const char *check_params(const mpdata_params *p)
     if (p->nonos != 0 && p->nonos != 1) return "nonos must be 0 or 1";
     if (p->nonos && p->iord < 2) return "nonos needs iord >= 2";
     if (!(p->eps > 0.0) || !isfinite(p->eps)) return "eps must be finite and > 0";
-    if (p->flags & ~(MPDATA_FLAG_NO_GRAPH | MPDATA_FLAG_VSIGN)) return "unknown flag bits";
+    if (p->flags & ~(MPDATA_FLAG_NO_GRAPH | MPDATA_FLAG_VSIGN | MPDATA_FLAG_DIV))
+        return "unknown flag bits";
     if (p->reserved != 0) return "reserved must be 0";
     int count = 0;
     mpd::tile_shapes(&count);
     if (p->tile < 0 || p->tile > count) return "tile id out of range";
     if (p->iord > 2 && p->tile != 0 && p->tile != default_tile(p->dtype, p->bc))
         return "iord > 2 runs on the default launch shape (tile 0)";
-    if ((p->flags & MPDATA_FLAG_VSIGN) && p->tile != 0 &&
+    if ((p->flags & (MPDATA_FLAG_VSIGN | MPDATA_FLAG_DIV)) && p->tile != 0 &&
         (shape_of(p->tile).rx != 32 || (shape_of(p->tile).ry != 24 && shape_of(p->tile).ry != 32)))
-        return "the variable-sign option runs on the 32x24 and 32x32 launch shapes (tile 0, 2 or 5)";
+        return "the variable-sign option and the divergent-flow term run on the 32x24 and 32x32 "
+               "launch shapes (tile 0, 2 or 5)";
     return nullptr;
 }
 
@@ -328,7 +330,8 @@ int device_cus()
 int variant_of(const mpdata_params &p)
 {
     return (p.bc == MPDATA_BC_OPEN ? mpd::kVariantOpen : 0) | (p.nonos ? mpd::kVariantNonos : 0) |
-           ((p.flags & MPDATA_FLAG_VSIGN) ? mpd::kVariantVsign : 0);
+           ((p.flags & MPDATA_FLAG_VSIGN) ? mpd::kVariantVsign : 0) |
+           ((p.flags & MPDATA_FLAG_DIV) ? mpd::kVariantDiv : 0);
 }
 
 int wg_per_cu(int dtype, int tile, int variant)
@@ -577,7 +580,8 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
         const mpdata_params &a = params[0], &b = params[i];
         if (a.dtype != b.dtype || a.bc != b.bc || a.iord != b.iord || a.nonos != b.nonos ||
             a.eps != b.eps || a.tile != b.tile ||
-            (a.flags & MPDATA_FLAG_VSIGN) != (b.flags & MPDATA_FLAG_VSIGN))
+            (a.flags & (MPDATA_FLAG_VSIGN | MPDATA_FLAG_DIV)) !=
+                (b.flags & (MPDATA_FLAG_VSIGN | MPDATA_FLAG_DIV)))
             return fail_to(errbuf, MPDATA_ENOTSUP,
                            "grid %d: a batch shares dtype, bc, iord, nonos, eps, tile and flags", i);
     }

@@ -37,8 +37,9 @@ struct TileShape {
 
 const TileShape *tile_shapes(int *count);
 
-// Kernel variants: open boundaries, limiter on, variable-sign option.
-enum { kVariantOpen = 1, kVariantNonos = 2, kVariantVsign = 4 };
+// Kernel variants: open boundaries, limiter on, variable-sign option,
+// divergent-flow term.
+enum { kVariantOpen = 1, kVariantNonos = 2, kVariantVsign = 4, kVariantDiv = 8 };
 
 // The persistent fused step kernel for (T, tile id, variant), as a function
 // pointer (for graph nodes and occupancy queries); nullptr if that variant is

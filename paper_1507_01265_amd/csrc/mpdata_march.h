@@ -148,9 +148,12 @@ template <> struct Tiny<float> { static constexpr float v = 1.17549435e-38f; };
 //       / (hs dA dBs dBt).
 // A denominator below the smallest normal number (all neighbouring psi1
 // within eps of zero, possible in FP32 only) gives V = 0.
-template <typename T>
+// With DIV the divergent-flow term -(1/4)(U/G) dv joins the numerator as
+// -(U/2) dv dA dBs dBt (dv: the centred divergence of the velocity field
+// across the face, the sum of the divergences of cells a and b).
+template <bool DIV = false, typename T>
 __device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi, T s_lo, T ut,
-                                             T t_hi, T t_lo, T eps)
+                                             T t_hi, T t_lo, T eps, T dv = T(0))
 {
     const T nA = pb - pa, dA = (pb + pa) + eps;
     const T nBs = s_hi - s_lo, dBs = (s_hi + s_lo) + eps;
@@ -158,7 +161,8 @@ __device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi
     const T P = dBs * dBt;
     const T c = fabs(U) * hs - T(2) * (U * U);
     const T cross = (us * nBs) * dBt + (ut * nBt) * dBs;
-    const T num = (c * nA) * P - (T(0.25) * U * dA) * cross;
+    T num = (c * nA) * P - (T(0.25) * U * dA) * cross;
+    if constexpr (DIV) num = num - (T(0.5) * U * dv) * (dA * P);
     const T den = (hs * dA) * P;
     if constexpr (sizeof(T) == 8) {
         // FP64: the guard never fires on real data; divide unconditionally
@@ -276,7 +280,7 @@ template <typename T> struct PlaneB {
 enum { kModeStep = 0, kModeHead = 1, kModeMid = 2, kModeLast = 3 };
 
 // LDS planes of one workgroup (each padded by one cell on every side).
-template <typename T, int RX, int RY, int MODE> struct Smem {
+template <typename T, int RX, int RY, int MODE, bool DIVP = false> struct Smem {
     static constexpr int PX = RX + 2, PP = PX * (RY + 2);
     // kModeStep/kModeHead: psi^n plane t (its ring holds real data);
     // kModeMid/kModeLast: the running upper bound of plane t, with the lower
@@ -286,6 +290,8 @@ template <typename T, int RX, int RY, int MODE> struct Smem {
     T sPm[PM];
     T sQ[3][PP];                         // psi1, planes t-2 .. t in fixed slots
     T sC1[PP], sC2[PP], sC3[PP], sH[PP]; // Courant column sums, h: plane t-1
+    static constexpr int PD = DIVP ? PP : 1;
+    T sD[PD];                            // cell divergence of the velocity field: plane t-1
     // x-face fluxes go through LDS only where x-neighbours are not
     // exchanged between lanes (FP32)
     static constexpr int PX1 = sizeof(T) == 8 ? 1 : PP;
@@ -296,10 +302,10 @@ template <typename T, int RX, int RY, int MODE> struct Smem {
 
 // One workgroup advances the output tile (tx, ty) of grid g through planes
 // [z0, z1): psi[flip] -> psi[1 - flip].
-template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN, int MODE>
+template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN, bool DIV, int MODE>
 __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io, int flip, int tx,
                                       int ty, int z0, int z1, double eps_d,
-                                      Smem<T, RX, RY, MODE> &sm)
+                                      Smem<T, RX, RY, MODE, DIV> &sm)
 {
     constexpr bool kPass = MODE >= kModeMid;                      // S1 replaced by a load
     constexpr bool kOuts = MODE == kModeHead || MODE == kModeMid; // velocity + bounds out
@@ -312,6 +318,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     auto &sQ = sm.sQ;
     T *__restrict__ sC1 = sm.sC1, *__restrict__ sC2 = sm.sC2, *__restrict__ sC3 = sm.sC3;
     T *__restrict__ sH = sm.sH, *__restrict__ sFA1 = sm.sFA1, *__restrict__ sFA2 = sm.sFA2;
+    T *__restrict__ sD = sm.sD;
     L *__restrict__ sBU = sm.sBU, *__restrict__ sBD = sm.sBD;
     T *__restrict__ sFC1 = sm.sFC1, *__restrict__ sFC2 = sm.sFC2;
 
@@ -470,6 +477,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     constexpr bool kDpp = sizeof(T) == 8;
     T r_p1_m1 = T(0), r_p1_m2 = T(0), r_p1_m3 = T(0);
     T r_c1_m1 = T(0), r_c2_m1 = T(0), r_c3_m1 = T(0), r_h_m1 = T(0);
+    T r_d_m1 = T(0);  // divergence of the column's cell at plane t-1 (DIV)
     T v1_m2 = T(0), v2_m2 = T(0), v3_m1 = T(0); // V at plane t-2, V3 at face t-1
     T fa3_m1 = T(0);                            // antidiffusive flux, face t-1
     L bu_m2 = 1.0, bd_m2 = 1.0;                 // limiter factors (capped at 1), plane t-2
@@ -487,6 +495,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         // own-column values of planes t-1 .. t-3
         const T p1_m1 = r_p1_m1, p1_m2 = r_p1_m2, p1_m3 = r_p1_m3;
         const T c1_m1 = r_c1_m1, c2_m1 = r_c2_m1, c3_m1 = r_c3_m1, h_m1 = r_h_m1;
+        const T d_m1 = r_d_m1;
 
         // limiter factors of plane t-2 (computed last iteration) for the
         // neighbours' corrective pass after (F); their previous contents were
@@ -546,6 +555,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         const T c1_c = curA.u1lo + curA.u1hi;
         const T c2_c = curA.u2lo + curA.u2hi;
         const T c3_c = cur.u3lo + nx1.u3lo;
+        // divergence of the velocity field in the cell of plane t (DIV)
+        T d_c = T(0);
+        if constexpr (DIV)
+            d_c = ((curA.u1hi - curA.u1lo) + (curA.u2hi - curA.u2lo)) + (nx1.u3lo - cur.u3lo);
         __syncthreads();  // (D) psi1(t) and the limiter factors of t-2 are visible
 
         T v1, v2, v3, fa1 = T(0), fa2 = T(0), fa3_c = T(0);
@@ -588,19 +601,22 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             }
             {
                 // x-face between a = (lx-1) and b = own; transverse axes y then z
-                T h_a, c2_a, c3_a, qyp_a, qym_a, phi_a, plo_a;
+                T h_a, c2_a, c3_a, qyp_a, qym_a, phi_a, plo_a, d_a = T(0);
                 if constexpr (kDpp) {
                     h_a = from_lo(h_m1), c2_a = from_lo(c2_m1), c3_a = from_lo(c3_m1);
                     qyp_a = from_lo(qyp_), qym_a = from_lo(qym_);
+                    if constexpr (DIV) d_a = from_lo(d_m1);
                     phi_a = chi ? qa : pc_xlo, plo_a = clo ? qa : p2_xm;
                 } else {
                     h_a = sH[q + XM], c2_a = sC2[q + XM], c3_a = sC3[q + XM];
                     qyp_a = Qc[q + XM + cyp], qym_a = Qc[q + XM + cym];
                     phi_a = Qhi[q + XM], plo_a = Qlo[q + XM];
+                    if constexpr (DIV) d_a = sD[q + XM];
                 }
-                v1 = pseudo_velocity(u1_m1, h_a + h_m1, av(qa), av(p1_m1), c2_a + c2_m1,
-                                     av(qyp_) + av(qyp_a), av(qym_) + av(qym_a), c3_a + c3_m1,
-                                     av(p1_hi) + av(phi_a), av(p1_lo) + av(plo_a), eps);
+                v1 = pseudo_velocity<DIV>(u1_m1, h_a + h_m1, av(qa), av(p1_m1), c2_a + c2_m1,
+                                          av(qyp_) + av(qyp_a), av(qym_) + av(qym_a), c3_a + c3_m1,
+                                          av(p1_hi) + av(phi_a), av(p1_lo) + av(plo_a), eps,
+                                          d_a + d_m1);
                 if (zero_v1) v1 = T(0);
             }
             // the three faces are scheduled one after another: each face's
@@ -617,10 +633,13 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                     qd_xp = Qc[q + YM + cxp];
                     qd_xm = Qc[q + YM + cxm];
                 }
-                v2 = pseudo_velocity(u2_m1, sH[q + YM] + h_m1, av(qd), av(p1_m1),
-                                     sC3[q + YM] + c3_m1, av(p1_hi) + av(Qhi[q + YM]),
-                                     av(p1_lo) + av(Qlo[q + YM]), sC1[q + YM] + c1_m1,
-                                     av(qxp_) + av(qd_xp), av(qxm_) + av(qd_xm), eps);
+                T d_ya = T(0);
+                if constexpr (DIV) d_ya = sD[q + YM];
+                v2 = pseudo_velocity<DIV>(u2_m1, sH[q + YM] + h_m1, av(qd), av(p1_m1),
+                                          sC3[q + YM] + c3_m1, av(p1_hi) + av(Qhi[q + YM]),
+                                          av(p1_lo) + av(Qlo[q + YM]), sC1[q + YM] + c1_m1,
+                                          av(qxp_) + av(qd_xp), av(qxm_) + av(qd_xm), eps,
+                                          d_ya + d_m1);
                 if (zero_v2) v2 = T(0);
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -635,9 +654,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                     pc_xp = Qb[q + cxp];
                     pc_xm = Qb[q + cxm];
                 }
-                v3 = pseudo_velocity(cur.u3lo, h_m1 + curA.h, av(p1_m1), av(p1_c), c1_m1 + c1_c,
-                                     av(pc_xp) + av(qxp_), av(pc_xm) + av(qxm_), c2_m1 + c2_c,
-                                     av(Qb[q + cyp]) + av(qyp_), av(Qb[q + cym]) + av(qym_), eps);
+                v3 = pseudo_velocity<DIV>(cur.u3lo, h_m1 + curA.h, av(p1_m1), av(p1_c),
+                                          c1_m1 + c1_c, av(pc_xp) + av(qxp_), av(pc_xm) + av(qxm_),
+                                          c2_m1 + c2_c, av(Qb[q + cyp]) + av(qyp_),
+                                          av(Qb[q + cym]) + av(qym_), eps, d_m1 + d_c);
             }
             if (OPEN && (t <= 0 || t >= nz)) v3 = T(0);
             if (NONOS) {
@@ -729,6 +749,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         sC2[q] = c2_c;
         sC3[q] = c3_c;
         sH[q] = curA.h;
+        if constexpr (DIV) sD[q] = d_c;
         rng = load_ring(ka);  // plane t+2
         if constexpr (kPass && NONOS) {
             // running bounds of plane t+1 for the next iteration's stencil;
@@ -770,6 +791,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             r_c2_m1 = c2_c;
             r_c3_m1 = c3_c;
             r_h_m1 = curA.h;
+            r_d_m1 = d_c;
         }
         curA = nxA;
         cur = nx1;
@@ -801,13 +823,14 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
 // Every LDS plane starts at zero, so values computed from not-yet-written
 // slots in the first iterations of a march stay finite (they never reach an
 // output).
-template <typename T, int RX, int RY, int MODE>
-__device__ __forceinline__ void smem_clear(Smem<T, RX, RY, MODE> &sm)
+template <typename T, int RX, int RY, int MODE, bool DIVP>
+__device__ __forceinline__ void smem_clear(Smem<T, RX, RY, MODE, DIVP> &sm)
 {
-    using S = Smem<T, RX, RY, MODE>;
+    using S = Smem<T, RX, RY, MODE, DIVP>;
     for (int i = threadIdx.x; i < S::PP; i += RX * RY) {
         sm.sP[i] = T(0);
         if (i < S::PM) sm.sPm[i] = T(0);
+        if (i < S::PD) sm.sD[i] = T(0);
         sm.sQ[0][i] = sm.sQ[1][i] = sm.sQ[2][i] = T(0);
         sm.sC1[i] = sm.sC2[i] = sm.sC3[i] = sm.sH[i] = T(0);
         sm.sFA2[i] = sm.sFC2[i] = T(0);

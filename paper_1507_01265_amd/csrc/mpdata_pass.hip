@@ -31,40 +31,47 @@ static_assert(kPassHead == kModeHead && kPassMid == kModeMid && kPassLast == kMo
 // Persistent kernel of one pass: workgroup b walks the segments
 // [wg_begin[b], wg_begin[b+1]) of the plan, as the step kernel does;
 // grids[g].psi[0] is the input iterate and grids[g].psi[1] the output.
-template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN, int MODE>
+template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN, bool DIV, int MODE>
 __global__ __launch_bounds__(RX * RY) void pass_kernel(const GridDesc<T> *__restrict__ grids,
                                                       const PassIO<T> *__restrict__ io,
                                                       const Segment *__restrict__ segs,
                                                       const int *__restrict__ wg_begin, double eps)
 {
-    __shared__ Smem<T, RX, RY, MODE> sm;
+    __shared__ Smem<T, RX, RY, MODE, DIV> sm;
     smem_clear(sm);
     const int b = wg_begin[blockIdx.x], e = wg_begin[blockIdx.x + 1];
     for (int s = b; s < e; ++s) {
         const Segment sg = segs[s];
-        march<T, RX, RY, OPEN, NONOS, VSIGN, MODE>(grids[sg.grid], io[sg.grid], 0, sg.tx, sg.ty,
-                                                   sg.z0, sg.z1, eps, sm);
+        march<T, RX, RY, OPEN, NONOS, VSIGN, DIV, MODE>(grids[sg.grid], io[sg.grid], 0, sg.tx,
+                                                        sg.ty, sg.z0, sg.z1, eps, sm);
         __syncthreads();
     }
 }
 
-template <typename T, int RX, int RY, bool OPEN, int MODE>
+template <typename T, int RX, int RY, bool OPEN, bool DIV, int MODE>
 static const void *pick_options(bool nonos, bool vsign)
 {
     if (vsign)
-        return nonos ? (const void *)pass_kernel<T, RX, RY, OPEN, true, true, MODE>
-                     : (const void *)pass_kernel<T, RX, RY, OPEN, false, true, MODE>;
-    return nonos ? (const void *)pass_kernel<T, RX, RY, OPEN, true, false, MODE>
-                 : (const void *)pass_kernel<T, RX, RY, OPEN, false, false, MODE>;
+        return nonos ? (const void *)pass_kernel<T, RX, RY, OPEN, true, true, DIV, MODE>
+                     : (const void *)pass_kernel<T, RX, RY, OPEN, false, true, DIV, MODE>;
+    return nonos ? (const void *)pass_kernel<T, RX, RY, OPEN, true, false, DIV, MODE>
+                 : (const void *)pass_kernel<T, RX, RY, OPEN, false, false, DIV, MODE>;
+}
+
+template <typename T, int RX, int RY, bool OPEN, int MODE>
+static const void *pick_div(bool nonos, bool vsign, bool div)
+{
+    return div ? pick_options<T, RX, RY, OPEN, true, MODE>(nonos, vsign)
+               : pick_options<T, RX, RY, OPEN, false, MODE>(nonos, vsign);
 }
 
 template <typename T, int RX, int RY, bool OPEN>
-static const void *pick_mode(int mode, bool nonos, bool vsign)
+static const void *pick_mode(int mode, bool nonos, bool vsign, bool div)
 {
     switch (mode) {
-    case kModeHead: return pick_options<T, RX, RY, OPEN, kModeHead>(nonos, vsign);
-    case kModeMid: return pick_options<T, RX, RY, OPEN, kModeMid>(nonos, vsign);
-    case kModeLast: return pick_options<T, RX, RY, OPEN, kModeLast>(nonos, vsign);
+    case kModeHead: return pick_div<T, RX, RY, OPEN, kModeHead>(nonos, vsign, div);
+    case kModeMid: return pick_div<T, RX, RY, OPEN, kModeMid>(nonos, vsign, div);
+    case kModeLast: return pick_div<T, RX, RY, OPEN, kModeLast>(nonos, vsign, div);
     default: return nullptr;
     }
 }
@@ -75,14 +82,14 @@ static const void *pick_mode(int mode, bool nonos, bool vsign)
 template <typename T> const void *pass_kernel_ptr(int tile, int variant, int mode)
 {
     const bool open = variant & kVariantOpen, nonos = variant & kVariantNonos;
-    const bool vsign = variant & kVariantVsign;
+    const bool vsign = variant & kVariantVsign, div = variant & kVariantDiv;
     if constexpr (sizeof(T) == 4) {
-        if (open) return tile == 2 ? pick_mode<T, 32, 32, true>(mode, nonos, vsign) : nullptr;
-        return tile == 5 ? pick_mode<T, 32, 24, false>(mode, nonos, vsign) : nullptr;
+        if (open) return tile == 2 ? pick_mode<T, 32, 32, true>(mode, nonos, vsign, div) : nullptr;
+        return tile == 5 ? pick_mode<T, 32, 24, false>(mode, nonos, vsign, div) : nullptr;
     } else {
         if (tile != 5) return nullptr;
-        return open ? pick_mode<T, 32, 24, true>(mode, nonos, vsign)
-                    : pick_mode<T, 32, 24, false>(mode, nonos, vsign);
+        return open ? pick_mode<T, 32, 24, true>(mode, nonos, vsign, div)
+                    : pick_mode<T, 32, 24, false>(mode, nonos, vsign, div);
     }
 }
 

@@ -15,20 +15,20 @@ namespace mpd {
 // advances each one time step.  With seg_ticks non-null the wall-clock
 // duration of every segment is recorded (the per-block speeds a plan tuner
 // measures while all workgroups run together).
-template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN>
+template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN, bool DIV>
 __global__ __launch_bounds__(RX * RY) void step_kernel(const GridDesc<T> *__restrict__ grids,
                                                       const Segment *__restrict__ segs,
                                                       const int *__restrict__ wg_begin, int flip,
                                                       double eps, long long *__restrict__ seg_ticks)
 {
-    __shared__ Smem<T, RX, RY, kModeStep> sm;
+    __shared__ Smem<T, RX, RY, kModeStep, DIV> sm;
     smem_clear(sm);
     const int b = wg_begin[blockIdx.x], e = wg_begin[blockIdx.x + 1];
     for (int s = b; s < e; ++s) {
         const Segment sg = segs[s];
         const long long t_start = seg_ticks ? (long long)wall_clock64() : 0;
-        march<T, RX, RY, OPEN, NONOS, VSIGN, kModeStep>(grids[sg.grid], PassIO<T>{}, flip, sg.tx,
-                                                        sg.ty, sg.z0, sg.z1, eps, sm);
+        march<T, RX, RY, OPEN, NONOS, VSIGN, DIV, kModeStep>(grids[sg.grid], PassIO<T>{}, flip,
+                                                             sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
         __syncthreads();
         // optional per-segment duration (workgroup-uniform; one lane stores)
         if (seg_ticks && threadIdx.x == 0) seg_ticks[s] = (long long)wall_clock64() - t_start;
@@ -71,25 +71,31 @@ const TileShape *tile_shapes(int *count)
     return shapes;
 }
 
-template <typename T, int RX, int RY, bool VSIGN> static const void *pick4(bool open, bool nonos)
+template <typename T, int RX, int RY, bool VSIGN, bool DIV>
+static const void *pick4(bool open, bool nonos)
 {
     if (open)
-        return nonos ? (const void *)step_kernel<T, RX, RY, true, true, VSIGN>
-                     : (const void *)step_kernel<T, RX, RY, true, false, VSIGN>;
-    return nonos ? (const void *)step_kernel<T, RX, RY, false, true, VSIGN>
-                 : (const void *)step_kernel<T, RX, RY, false, false, VSIGN>;
+        return nonos ? (const void *)step_kernel<T, RX, RY, true, true, VSIGN, DIV>
+                     : (const void *)step_kernel<T, RX, RY, true, false, VSIGN, DIV>;
+    return nonos ? (const void *)step_kernel<T, RX, RY, false, true, VSIGN, DIV>
+                 : (const void *)step_kernel<T, RX, RY, false, false, VSIGN, DIV>;
 }
 
-// The variable-sign option is built for the default launch shapes only
-// (32x24 and 32x32 regions).
+// The variable-sign option and the divergent-flow term are built for the
+// default launch shapes only (32x24 and 32x32 regions).
 template <typename T, int RX, int RY> static const void *pick(int variant)
 {
     const bool open = variant & kVariantOpen, nonos = variant & kVariantNonos;
-    if (variant & kVariantVsign) {
-        if constexpr (RX == 32 && (RY == 24 || RY == 32)) return pick4<T, RX, RY, true>(open, nonos);
+    const bool vsign = variant & kVariantVsign, div = variant & kVariantDiv;
+    if (vsign || div) {
+        if constexpr (RX == 32 && (RY == 24 || RY == 32)) {
+            if (vsign && div) return pick4<T, RX, RY, true, true>(open, nonos);
+            if (vsign) return pick4<T, RX, RY, true, false>(open, nonos);
+            return pick4<T, RX, RY, false, true>(open, nonos);
+        }
         return nullptr;
     }
-    return pick4<T, RX, RY, false>(open, nonos);
+    return pick4<T, RX, RY, false, false>(open, nonos);
 }
 
 template <typename T> const void *step_kernel_ptr(int tile, int variant)

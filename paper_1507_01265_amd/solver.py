@@ -23,9 +23,10 @@ def _check_runtime():
 
 
 def make_params(shape, dtype=torch.float64, bc="periodic", iord=2, nonos=True, eps=1e-15, tile=0,
-                graph=True, vsign=False):
+                graph=True, vsign=False, div=False):
     nz, ny, nx = shape
-    flags = (0 if graph else _lib.MPDATA_FLAG_NO_GRAPH) | (_lib.MPDATA_FLAG_VSIGN if vsign else 0)
+    flags = ((0 if graph else _lib.MPDATA_FLAG_NO_GRAPH) | (_lib.MPDATA_FLAG_VSIGN if vsign else 0)
+             | (_lib.MPDATA_FLAG_DIV if div else 0))
     return _lib.mpdata_params(nx, ny, nz, DTYPES[dtype], BC[bc], iord, int(bool(nonos)), tile,
                               flags, 0, eps)
 
@@ -34,6 +35,8 @@ class Solver:
     """``Solver(psi, u1, u2, u3, h, bc=..., iord=2, nonos=True, vsign=False)``.
 
     vsign: fields of variable sign (|psi1| in the pseudo-velocity ratios).
+    div: the divergent-flow term of the pseudo-velocity (flows that are not
+    divergence-free).
 
     psi: [nz][ny][nx] device tensor (float64 or float32), updated in place by
     ``step``; u1 [nz][ny][nx+1], u2 [nz][ny+1][nx], u3 [nz+1][ny][nx], h like
@@ -41,7 +44,7 @@ class Solver:
     """
 
     def __init__(self, psi, u1, u2, u3, h, *, bc="periodic", iord=2, nonos=True, eps=1e-15,
-                 tile=0, graph=True, stream=None, vsign=False):
+                 tile=0, graph=True, stream=None, vsign=False, div=False):
         if not torch.cuda.is_available():
             raise RuntimeError("libmpdata needs a GPU")
         _lib.load()
@@ -56,7 +59,8 @@ class Solver:
                 raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {want[name]}")
             if not t.is_cuda or not t.is_contiguous() or t.dtype != psi.dtype:
                 raise ValueError(f"{name}: needs a contiguous {psi.dtype} device tensor")
-        self.params = make_params(psi.shape, psi.dtype, bc, iord, nonos, eps, tile, graph, vsign)
+        self.params = make_params(psi.shape, psi.dtype, bc, iord, nonos, eps, tile, graph, vsign,
+                                  div)
         self.stream = stream if stream is not None else torch.cuda.current_stream(psi.device)
         ws_bytes = _lib.mpdata_workspace_bytes(self.params)
         if ws_bytes == 0:

@@ -88,6 +88,16 @@ def test_vsign_flag_needs_a_default_launch_shape():
     assert _lib.mpdata_workspace_bytes(_params(flags=8)) == 0
 
 
+def test_div_flag_needs_a_default_launch_shape():
+    dv = _lib.MPDATA_FLAG_DIV
+    for flags in (dv, dv | _lib.MPDATA_FLAG_VSIGN):
+        assert _lib.mpdata_workspace_bytes(_params(flags=flags)) > 0
+        for t in (2, 5):
+            assert _lib.mpdata_workspace_bytes(_params(flags=flags, tile=t)) > 0
+        for t in (1, 3, 4, 6):
+            assert _lib.mpdata_workspace_bytes(_params(flags=flags, tile=t)) == 0
+
+
 def test_more_corrective_passes_need_chain_buffers():
     """iord > 2: one more iterate, the three velocity face arrays and (with
     the limiter) the two running-bound arrays; a second set from iord 4 on;
