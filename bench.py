@@ -40,6 +40,9 @@ WORKLOADS = {
                             "passes: the fused step, then a second pass launch)"),
     "rotation-fp32-iord3": ("rotation", "f32",
                             "rotation 512x256x64 periodic FP32 + FP64 limiter, limiter on, iord 3"),
+    "divergent-fp64": ("divergent", "f64",
+                       "rotation 512x256x64 periodic FP64 with a compressible cosine part on every "
+                       "axis (divergent flow), divergent-flow term on, limiter on, iord 2"),
     "batched-fp32": ("batched", "f32",
                      "96 uneven periodic grids (nx, ny log-uniform in [32, 384], nz in [16, 64]), "
                      "FP32 + FP64 limiter, constant Courant per grid, one persistent launch per "
@@ -65,8 +68,9 @@ def algorithmic_bytes(shape, word):
     return word * (3 * n + faces)
 
 
-# corrective passes of a workload (iord), 2 unless named here
-IORD = {"rotation-fp64-iord3": 3, "rotation-fp32-iord3": 3}
+# scheme options of a workload (iord 2, no divergent-flow term unless named here)
+OPTIONS = {"rotation-fp64-iord3": {"iord": 3}, "rotation-fp32-iord3": {"iord": 3},
+           "divergent-fp64": {"div": True}}
 
 
 def chain_bytes(shape, word, iord, nonos=True):
@@ -116,17 +120,19 @@ def measured_traffic(workload):
 
 def make_fields(kind):
     from paper_1507_01265_amd import inputs
+    if kind == "divergent":
+        return inputs.divergent_rotation()
     return inputs.rotation() if kind == "rotation" else inputs.streamfunction()
 
 
-def time_gpu(fields, dtype_tag, steps, warmup, tile=0, iord=2):
+def time_gpu(fields, dtype_tag, steps, warmup, tile=0, iord=2, div=False):
     import numpy as np
     import torch
     from paper_1507_01265_amd.solver import Solver
 
     tdt = torch.float64 if dtype_tag == "f64" else torch.float32
     f = fields if dtype_tag == "f64" else fields.astype(np.float32)
-    s = Solver.from_numpy(f, dtype=tdt, device="cuda", tile=tile, iord=iord)
+    s = Solver.from_numpy(f, dtype=tdt, device="cuda", tile=tile, iord=iord, div=div)
     stream = s.stream
     m0 = s.mass()
     if warmup:
@@ -145,7 +151,7 @@ def time_gpu(fields, dtype_tag, steps, warmup, tile=0, iord=2):
     return {"ms": ms, "mass0": m0, "mass1": m1, "psi_min": psi_min}
 
 
-def cpu_baseline(fields, budget_s=12.0, max_steps=40, iord=2):
+def cpu_baseline(fields, budget_s=12.0, max_steps=40, iord=2, div=False):
     """The FP64 oracle as it stands, stepped on the host until the budget is
     spent (at least 2 steps)."""
     import oracle
@@ -154,7 +160,7 @@ def cpu_baseline(fields, budget_s=12.0, max_steps=40, iord=2):
     steps = 0
     t0 = time.perf_counter()
     while True:
-        psi = oracle.step(psi, f.u1, f.u2, f.u3, f.h, bc=f.bc, iord=iord)
+        psi = oracle.step(psi, f.u1, f.u2, f.u3, f.h, bc=f.bc, iord=iord, div=div)
         steps += 1
         el = time.perf_counter() - t0
         if (steps >= 2 and el >= budget_s) or steps >= max_steps:
@@ -363,8 +369,9 @@ def main():
     word = 8 if dtag == "f64" else 4
 
     print(f"# timing {args.steps} steps after {args.warmup} warmup", file=sys.stderr, flush=True)
-    iord = IORD.get(args.workload, 2)
-    g = time_gpu(fields, dtag, args.steps, args.warmup, args.tile, iord)
+    iord = OPTIONS.get(args.workload, {}).get("iord", 2)
+    div = OPTIONS.get(args.workload, {}).get("div", False)
+    g = time_gpu(fields, dtag, args.steps, args.warmup, args.tile, iord, div)
     ms_per_step = g["ms"] / args.steps
     value = cells * args.steps / (g["ms"] / 1e3)
     abytes = algorithmic_bytes(fields.shape, word)
@@ -390,6 +397,7 @@ def main():
         "data": "synthetic (seeded generator, resident in HBM)",
         "config": {"workload": desc, "nx": nx, "ny": ny, "nz": nz,
                    "bc": "periodic" if fields.bc == 0 else "open", "iord": iord, "nonos": True,
+                   "divergent_flow_term": div,
                    "tile": tile, "output_tile": f"{tx}x{ty}", "threads_per_workgroup": threads},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
@@ -405,7 +413,7 @@ def main():
         import oracle
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         f64 = fields if dtag == "f64" else fields.astype("float32").as_f64()
-        steps, el = cpu_baseline(f64, args.cpu_budget, iord=iord)
+        steps, el = cpu_baseline(f64, args.cpu_budget, iord=iord, div=div)
         line["cpu_baseline"] = {"value": cells * steps / el, "unit": "cell-updates/s",
                                 "cores": oracle.threads(), "kind": "oracle",
                                 "sample": f"{nx}x{ny}x{nz} {args.workload} inputs, {steps} FP64 "

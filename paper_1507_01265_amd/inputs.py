@@ -145,6 +145,24 @@ def rotation(seed: int = 1002, shape=(64, 256, 512), u3_value=0.1) -> Fields:
     return Fields(psi, u1, u2, u3, h, BC_PERIODIC)
 
 
+def divergent_rotation(seed: int = 1004, shape=(64, 256, 512), umax=0.35, amp=0.05) -> Fields:
+    """The rotation workload made divergent: the solid-body flow scaled to
+    max |u2| = umax plus a compressible part amp cos(2 pi f/n) on the faces of
+    every axis (amp/2 along z), so every cell has a nonzero divergence; the
+    outflow of a cell stays below the smallest h (0.8)."""
+    f = rotation(seed, shape)
+    nz, ny, nx = shape
+    k = umax / 0.5
+    u1 = f.u1 * k + amp * np.cos(2 * math.pi * np.arange(nx + 1) / nx)[None, None, :]
+    u2 = f.u2 * k + amp * np.cos(2 * math.pi * np.arange(ny + 1) / ny)[None, :, None]
+    u3 = f.u3 + 0.5 * amp * np.cos(2 * math.pi * np.arange(nz + 1) / nz)[:, None, None]
+    # periodic: face n is face 0, bit for bit
+    u1[..., nx] = u1[..., 0]
+    u2[:, ny, :] = u2[:, 0, :]
+    u3[nz] = u3[0]
+    return Fields(f.psi, u1, u2, u3, f.h, BC_PERIODIC)
+
+
 def streamfunction(seed: int = 1003, shape=(64, 512, 1024), umax=0.4) -> Fields:
     """Open domain, divergence-free x-y flow from a quantised streamfunction."""
     rng = _rng(seed)

@@ -120,3 +120,11 @@ def test_full_size_divergent_fp64(orc):
     want = oracle_run(orc, f, 2, div=True)
     got = gpu_run(f, 2, div=True)
     assert rel_linf(got, want) <= 1e-12
+
+
+def test_parity_benchmark_flow(orc):
+    """The benchmark's divergent rotation flow at 128x64x16, 4 steps."""
+    f = inputs.divergent_rotation(shape=(16, 64, 128))
+    want = oracle_run(orc, f, 4, div=True)
+    got = gpu_run(f, 4, div=True)
+    assert rel_linf(got, want) <= 1e-12
