@@ -146,8 +146,10 @@ template <> struct Tiny<float> { static constexpr float v = 1.17549435e-38f; };
 // is evaluated over one common denominator, so a face costs one division:
 //   V = [(|U| hs - 2U^2) nA dBs dBt - (U dA/4)(us nBs dBt + ut nBt dBs)]
 //       / (hs dA dBs dBt).
-// A denominator below the smallest normal number (all neighbouring psi1
-// within eps of zero, possible in FP32 only) gives V = 0.
+// A denominator below the smallest normal number in magnitude (all
+// neighbouring psi1 within eps of zero, possible in FP32 only) gives V = 0;
+// a negative one (a field below zero without the variable-sign option)
+// divides like any other.
 // With DIV the divergent-flow term -(1/4)(U/G) dv joins the numerator as
 // -(U/2) dv dA dBs dBt (dv: the centred divergence of the velocity field
 // across the face, the sum of the divergences of cells a and b).
@@ -164,16 +166,17 @@ __device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi
     T num = (c * nA) * P - (T(0.25) * U * dA) * cross;
     if constexpr (DIV) num = num - (T(0.5) * U * dv) * (dA * P);
     const T den = (hs * dA) * P;
+    const bool ok = fabs(den) >= Tiny<T>::v;
     if constexpr (sizeof(T) == 8) {
         // FP64: the guard never fires on real data; divide unconditionally
         // and select, with no branch around the division
-        const T v = div_nr(num, fmax(den, Tiny<T>::v));
-        return den >= Tiny<T>::v ? v : T(0);
+        const T v = div_nr(num, ok ? den : T(1));
+        return ok ? v : T(0);
     } else {
         // FP32: the guard fires wherever psi1 vanishes around the face (eps^3
         // underflows), and waves lying wholly in such a region skip the
         // division
-        return den >= Tiny<T>::v ? div_nr(num, den) : T(0);
+        return ok ? div_nr(num, den) : T(0);
     }
 }
 

@@ -324,3 +324,28 @@ def test_full_size_streamfunction_fp32(orc):
     want = oracle_run(orc, f.as_f64(), 1)
     got = gpu_run(f, 1, dtype=torch.float32)
     assert rel_linf(got, want) <= 2e-6 and rel_l2(got, want) <= 5e-7
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_negative_field_parity_fp64(orc, bc):
+    """A field below zero everywhere, without the variable-sign option and
+    without the limiter (which assumes psi >= 0): every ratio denominator is
+    negative and far from zero, so the common denominator of the
+    pseudo-velocity is negative and must divide like a positive one."""
+    import dataclasses
+    f = inputs.random_smooth(36, (13, 45, 70), bc=bc, cmax=0.15)
+    f = dataclasses.replace(f, psi=-f.psi)
+    assert f.psi.max() < -0.3
+    want = oracle_run(orc, f, 4, nonos=False)
+    got = gpu_run(f, 4, nonos=False)
+    assert rel_linf(got, want) <= 1e-12
+
+
+def test_negative_field_parity_fp32(orc):
+    import dataclasses
+    f = inputs.random_smooth(37, (13, 45, 70), cmax=0.15)
+    f = dataclasses.replace(f, psi=-f.psi).astype(np.float32)
+    n = 4
+    want = oracle_run(orc, f.as_f64(), n, nonos=False)
+    got = gpu_run(f, n, dtype=torch.float32, nonos=False)
+    assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
