@@ -137,10 +137,14 @@ template <> struct Tiny<float> { static constexpr float v = 1.17549435e-38f; };
 // is evaluated over one common denominator, so a face costs one division:
 //   V = [(|U| hs - 2U^2) nA dBs dBt - (U dA/4)(us nBs dBt + ut nBt dBs)]
 //       / (hs dA dBs dBt).
-// A denominator below the smallest normal number in magnitude (all
-// neighbouring psi1 within eps of zero, possible in FP32 only) gives V = 0;
-// a negative one (a field below zero without the variable-sign option)
-// divides like any other.
+// FP64 divides as written: for psi1 >= 0 (or the variable-sign option) every
+// ratio denominator is at least eps, so the common one is at least
+// hs eps^3 (about 1e-45), far inside the normal range; only a field of both
+// signs without the variable-sign option can zero it, and then V is Inf or
+// NaN exactly where the separate ratios divide by zero.  In FP32 eps^3
+// underflows: a common denominator below the smallest normal number in
+// magnitude (all neighbouring psi1 within eps of zero) gives V = 0.  A
+// negative denominator (a field below zero) divides like any other.
 // With DIV the divergent-flow term -(1/4)(U/G) dv joins the numerator as
 // -(U/2) dv dA dBs dBt (dv: the centred divergence of the velocity field
 // across the face, the sum of the divergences of cells a and b).
@@ -157,28 +161,25 @@ __device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi
     T num = (c * nA) * P - (T(0.25) * U * dA) * cross;
     if constexpr (DIV) num = num - (T(0.5) * U * dv) * (dA * P);
     const T den = (hs * dA) * P;
-    const bool ok = fabs(den) >= Tiny<T>::v;
     if constexpr (sizeof(T) == 8) {
-        // FP64: the guard never fires on real data; divide unconditionally
-        // and select, with no branch around the division
-        const T v = div_nr(num, ok ? den : T(1));
-        return ok ? v : T(0);
+        return div_nr(num, den);
     } else {
         // FP32: the guard fires wherever psi1 vanishes around the face (eps^3
         // underflows), and waves lying wholly in such a region skip the
         // division
-        return ok ? div_nr(num, den) : T(0);
+        return fabs(den) >= Tiny<T>::v ? div_nr(num, den) : T(0);
     }
 }
 
 // Limited pseudo-velocity; the factors are in limiter precision (double)
 // and already capped at 1 (min(1, a, b) = min(min(1, a), min(1, b)) exactly).
+// min(1, f_p) pos(V) + min(1, f_n) neg(V) is the factor of V's own sign
+// times V (the other product is an exact zero).
 template <typename T>
 __device__ __forceinline__ T limited(T v, double bup_a, double bdn_a, double bup_b, double bdn_b)
 {
-    const T cp = T(fmin(bdn_a, bup_b));
-    const T cn = T(fmin(bup_a, bdn_b));
-    return cp * pos(v) + cn * neg(v);
+    const double c = v > T(0) ? fmin(bdn_a, bup_b) : fmin(bup_a, bdn_b);
+    return T(c) * v;
 }
 
 // Global memory is read and written through buffer descriptors: one
