@@ -92,14 +92,27 @@ def time_steps(batch, steps):
     return a.elapsed_time(b) / steps
 
 
+def option_tiles():
+    """Launch shapes built for the variable-sign option and the divergent-flow
+    term: the 32x24 and 32x32 regions."""
+    out = []
+    for t in range(1, _lib.mpdata_tile_count() + 1):
+        tx, ty, _ = _lib.mpdata_tile_info(t)
+        if tx + 4 == 32 and ty + 4 in (24, 32):
+            out.append(t)
+    return out
+
+
 def tune(grids, *, bc="periodic", nonos=True, eps=1e-15, tiles=None, steps=4, profiles=3,
-         verbose=False):
+         verbose=False, vsign=False, div=False):
     """Pick the launch shape and the block assignment for ``grids`` (list of
     5-tuples of device tensors).  The grids' psi is restored afterwards."""
     dtype = grids[0][0].dtype
     dt = _lib.MPDATA_FP32 if dtype == torch.float32 else _lib.MPDATA_FP64
     if tiles is None:
-        tiles = list(range(1, _lib.mpdata_tile_count() + 1))
+        tiles = (option_tiles() if (vsign or div)
+                 else list(range(1, _lib.mpdata_tile_count() + 1)))
+    opts = dict(bc=bc, nonos=nonos, eps=eps, vsign=vsign, div=div)
     shapes = [tuple(g[0].shape) for g in grids]
     saved = [g[0].clone() for g in grids]
     log = []
@@ -112,7 +125,7 @@ def tune(grids, *, bc="periodic", nonos=True, eps=1e-15, tiles=None, steps=4, pr
         static = segs[:, 4] - segs[:, 3] + PRIMING
         owner, loads0 = lpt(static, nwg)
         plan0 = (tile, *plan_from_owner(segs, owner, nwg))
-        b = Batch(grids, bc=bc, nonos=nonos, eps=eps, plan=plan0)
+        b = Batch(grids, plan=plan0, **opts)
         b.step(2)
         ms0 = time_steps(b, steps)
         ticks = np.median(np.stack([b.profile_step() for _ in range(profiles)]), axis=0)
@@ -125,7 +138,7 @@ def tune(grids, *, bc="periodic", nonos=True, eps=1e-15, tiles=None, steps=4, pr
             measured[key[tuple(r)]] = t
         owner1, loads1 = lpt(measured, nwg)
         plan1 = (tile, *plan_from_owner(segs, owner1, nwg))
-        b = Batch(grids, bc=bc, nonos=nonos, eps=eps, plan=plan1)
+        b = Batch(grids, plan=plan1, **opts)
         b.step(2)
         ms1 = time_steps(b, steps)
         b.close()

@@ -17,10 +17,13 @@ from .solver import BC, DTYPES, _check_runtime
 
 class Batch:
     """``Batch(grids, ...)`` with ``grids`` a list of 5-tuples of device
-    tensors ``(psi, u1, u2, u3, h)`` (shapes as for :class:`Solver`)."""
+    tensors ``(psi, u1, u2, u3, h)`` (shapes as for :class:`Solver`).
+    ``vsign`` and ``div`` select the variable-sign option and the
+    divergent-flow term for every grid (built for the 32x24 and 32x32
+    launch shapes)."""
 
     def __init__(self, grids, *, bc="periodic", nonos=True, eps=1e-15, tile=0, plan=None,
-                 graph=True, stream=None):
+                 graph=True, stream=None, vsign=False, div=False):
         if not torch.cuda.is_available():
             raise RuntimeError("libmpdata needs a GPU")
         _lib.load()
@@ -28,7 +31,8 @@ class Batch:
         if not grids:
             raise ValueError("empty batch")
         dtype = grids[0][0].dtype
-        flags = 0 if graph else _lib.MPDATA_FLAG_NO_GRAPH
+        flags = ((0 if graph else _lib.MPDATA_FLAG_NO_GRAPH)
+                 | (_lib.MPDATA_FLAG_VSIGN if vsign else 0) | (_lib.MPDATA_FLAG_DIV if div else 0))
         self.params = []
         for i, (psi, u1, u2, u3, h) in enumerate(grids):
             nz, ny, nx = psi.shape
@@ -41,6 +45,7 @@ class Batch:
         self.grids = grids
         self.dtype = dtype
         self.bc, self.nonos, self.eps = bc, nonos, eps
+        self.vsign, self.div = vsign, div
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         keep = None
         cplan = None

@@ -136,3 +136,14 @@ def test_null_and_misaligned_pointers_are_rejected():
 
 def test_destroy_is_null_safe():
     _lib.mpdata_destroy(None)
+
+
+def test_option_tiles_are_the_default_shapes():
+    """The tuner's shapes for the variable-sign option and the divergent-flow
+    term are exactly those the library accepts with those flags."""
+    from paper_1507_01265_amd import autotune
+    t = autotune.option_tiles()
+    assert sorted(t) == [2, 5]
+    for tile in range(1, _lib.mpdata_tile_count() + 1):
+        ok = _lib.mpdata_workspace_bytes(_params(flags=_lib.MPDATA_FLAG_DIV, tile=tile)) > 0
+        assert ok == (tile in t)

@@ -136,3 +136,33 @@ def test_autotune_small_batch():
     for i, f in enumerate(fs):
         np.testing.assert_array_equal(b.psi(i).cpu().numpy(), _single(f, 2, torch.float32))
     b.close()
+
+
+@pytest.mark.parametrize("opts", [dict(div=True), dict(vsign=True, div=True)])
+def test_batch_with_options_matches_single_grid(orc, opts):
+    """The variable-sign option and the divergent-flow term in a batch (one
+    launch for all grids) equal the single-grid path bit for bit and the
+    oracle to 1e-12; the tuner keeps to the shapes built for them."""
+    import dataclasses
+    from paper_1507_01265_amd import autotune
+    from paper_1507_01265_amd.batch import Batch
+    from paper_1507_01265_amd.solver import Solver
+    fs = _grids(5, 950)
+    if opts.get("vsign"):
+        fs = [dataclasses.replace(f, psi=f.psi - 1.0) for f in fs]
+    g = [tuple(torch.from_numpy(a).cuda() for a in (f.psi, f.u1, f.u2, f.u3, f.h)) for f in fs]
+    tuned = autotune.tune(g, steps=1, profiles=1, **opts)
+    assert tuned.plan[0] in autotune.option_tiles()
+    b = Batch(g, plan=tuned.plan, **opts)
+    b.step(3)
+    b.sync()
+    for i, f in enumerate(fs):
+        got = b.psi(i).cpu().numpy()
+        s = Solver.from_numpy(f, dtype=torch.float64, **opts)
+        s.step(3)
+        s.sync()
+        np.testing.assert_array_equal(got, s.psi.cpu().numpy())
+        s.close()
+        want = orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 3, **opts)
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), i
+    b.close()
