@@ -296,8 +296,13 @@ template <typename T, int RX, int RY, int MODE, bool DIVP = false> struct Smem {
 };
 
 // One workgroup advances the output tile (tx, ty) of grid g through planes
-// [z0, z1): psi[flip] -> psi[1 - flip].
-template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN, bool DIV, int MODE>
+// [z0, z1): psi[flip] -> psi[1 - flip].  OPXY: open (zero-gradient)
+// boundaries in x and y -- clamped addressing and redirected neighbours;
+// OPZ: open in z.  An open grid's tiles whose region and ring lie inside the
+// domain with a cell to spare (x_interior) run with OPXY false: there
+// clamping and wrapping are both the identity and no lane sits on a
+// boundary.
+template <typename T, int RX, int RY, bool OPXY, bool OPZ, bool NONOS, bool VSIGN, bool DIV, int MODE>
 __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io, int flip, int tx,
                                       int ty, int z0, int z1, double eps_d,
                                       Smem<T, RX, RY, MODE, DIV> &sm)
@@ -330,15 +335,15 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     const int q = (ly + 1) * PX + lx + 1;
 
     // in-plane offsets into the global arrays
-    const int cx = cell_of<OPEN>(gx, nx), cy = cell_of<OPEN>(gy, ny);
+    const int cx = cell_of<OPXY>(gx, nx), cy = cell_of<OPXY>(gy, ny);
     const unsigned pc_cells = (unsigned)nx * ny;
     const unsigned pc_u1 = (unsigned)(nx + 1) * ny;
     const unsigned pc_u2 = (unsigned)nx * (ny + 1);
     const unsigned o_c = cy * nx + cx;
-    const unsigned o_u1lo = cy * (nx + 1) + face_lo<OPEN>(gx, nx);
-    const unsigned o_u1hi = cy * (nx + 1) + face_hi<OPEN>(gx, nx);
-    const unsigned o_u2lo = face_lo<OPEN>(gy, ny) * nx + cx;
-    const unsigned o_u2hi = face_hi<OPEN>(gy, ny) * nx + cx;
+    const unsigned o_u1lo = cy * (nx + 1) + face_lo<OPXY>(gx, nx);
+    const unsigned o_u1hi = cy * (nx + 1) + face_hi<OPXY>(gx, nx);
+    const unsigned o_u2lo = face_lo<OPXY>(gy, ny) * nx + cx;
+    const unsigned o_u2hi = face_hi<OPXY>(gy, ny) * nx + cx;
     // The ring of the psi^n plane -- the padded LDS cells around the region,
     // 2 RY of them left and right, 2 RX below and above -- is loaded by the
     // first 2 (RX + RY) threads, one cell each (the other waves skip it).
@@ -358,7 +363,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         rgy = ty * TY - 2 + (side ? RY : -1);
         p_ring = (side ? RY + 1 : 0) * PX + col + 1;
     }
-    const unsigned o_ring = cell_of<OPEN>(rgy, ny) * nx + cell_of<OPEN>(rgx, nx);
+    const unsigned o_ring = cell_of<OPXY>(rgy, ny) * nx + cell_of<OPXY>(rgx, nx);
     // byte offsets within a plane (the host keeps every plane below 4 GiB)
     const unsigned b_c = o_c * (unsigned)sizeof(T);
     const unsigned b_u1lo = o_u1lo * (unsigned)sizeof(T), b_u1hi = o_u1hi * (unsigned)sizeof(T);
@@ -367,15 +372,15 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
 
     // cell-centred neighbour offsets: at an open boundary a read of the cell
     // beyond it is redirected to the cell itself (zero gradient)
-    const bool edge_lo = OPEN && gx <= 0, edge_hi = OPEN && gx >= nx - 1;
+    const bool edge_lo = OPXY && gx <= 0, edge_hi = OPXY && gx >= nx - 1;
     const int cxm = edge_lo ? 0 : XM;
     const int cxp = edge_hi ? 0 : XP;
-    const int cym = (OPEN && gy <= 0) ? 0 : YM;
-    const int cyp = (OPEN && gy >= ny - 1) ? 0 : YP;
+    const int cym = (OPXY && gy <= 0) ? 0 : YM;
+    const int cyp = (OPXY && gy >= ny - 1) ? 0 : YP;
 
     // boundary-normal faces of an open domain carry no antidiffusive flux
-    const bool zero_v1 = OPEN && (gx <= 0 || gx >= nx);
-    const bool zero_v2 = OPEN && (gy <= 0 || gy >= ny);
+    const bool zero_v1 = OPXY && (gx <= 0 || gx >= nx);
+    const bool zero_v2 = OPXY && (gy <= 0 || gy >= ny);
     const bool is_out = lx >= 2 && lx < RX - 2 && ly >= 2 && ly < RY - 2 && gx < nx && gy < ny;
     // Writers of the limited velocity (kModeHead, kModeMid): the lower x- and
     // y-faces of the output cells, and face nx (ny) of a row (column) from the
@@ -389,10 +394,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
 
     // plane index of position t along z: wrapped (periodic) or clamped (open);
     // the march advances it by one per iteration without a division
-    auto plane_of = [&](int t) { return cell_of<OPEN>(t, nz); };
-    auto zface_of = [&](int t) { return face_lo<OPEN>(t, nz); };
+    auto plane_of = [&](int t) { return cell_of<OPZ>(t, nz); };
+    auto zface_of = [&](int t) { return face_lo<OPZ>(t, nz); };
     auto next_plane = [&](int k, int t_next) {
-        if (OPEN) return clampi(t_next, 0, nz - 1);
+        if (OPZ) return clampi(t_next, 0, nz - 1);
         return k + 1 == nz ? 0 : k + 1;
     };
     auto load_a = [&](int k, PlaneA<T> &r) {
@@ -401,7 +406,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         const Rsrc u2p = plane_rsrc(g.u2, k, pc_u2);
         r.h = bload<T>(hp, b_c);
         r.u1lo = bload<T>(u1p, b_u1lo);
-        if (OPEN) {
+        if (OPXY) {
             r.u1hi = bload<T>(u1p, b_u1hi);
             r.u2lo = bload<T>(u2p, b_u2lo);
             r.u2hi = bload<T>(u2p, b_u2hi);
@@ -483,7 +488,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         constexpr int s0 = decltype(slot)::value;           // slot of plane t (held t-3)
         constexpr int s1 = (s0 + 2) % 3, s2 = (s0 + 1) % 3; // planes t-1, t-2
         load_a(ka, nxA);
-        load_b(kb, OPEN ? zface_of(t + 2) : kb, nx2);
+        load_b(kb, OPZ ? zface_of(t + 2) : kb, nx2);
         ka = kb;
         kb = next_plane(kb, t + 3);
         __syncthreads();  // (B) psi^n(t), sums/h of t-1, corrective y-fluxes of t-3 are visible
@@ -518,7 +523,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             // the in-plane 5-point stencil of plane t and the plane below it
             rh_c = rcp_nr(curA.h);
             p1_c = cur.pn;
-            const bool zlo = OPEN && t <= 0;
+            const bool zlo = OPZ && t <= 0;
             zmx_c = fmax(fmax(fmax(sP[q + cxm], sP[q + cxp]), fmax(sP[q + cym], sP[q + cyp])),
                          zlo ? M_c : fmax(M_c, M_m1));
             zmn_c = fmin(fmin(fmin(sPm[q + cxm], sPm[q + cxp]), fmin(sPm[q + cym], sPm[q + cyp])),
@@ -537,7 +542,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             rh_c = rcp_nr(curA.h);
             p1_c = cur.pn - (((f1hi - f1lo) + (f2hi - f2lo)) + (f3hi - f3_c)) * rh_c;
             // (at an open bottom the plane below t is t itself, already counted)
-            const bool zlo = OPEN && t <= 0;
+            const bool zlo = OPZ && t <= 0;
             zmx_c = fmax(fmax(fmax(pL, pR), fmax(pD, pU)), zlo ? cur.pn : fmax(cur.pn, pn_m1));
             zmn_c = fmin(fmin(fmin(pL, pR), fmin(pD, pU)), zlo ? cur.pn : fmin(cur.pn, pn_m1));
             if (MODE == kModeHead && NONOS && is_out && own_plane) {
@@ -562,7 +567,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         {
             // ---- S3 at plane p = t-1 (lower x- and y-faces) and on face t
             const int p = t - 1;
-            const bool clo = OPEN && p <= 0, chi = OPEN && p >= nz - 1;
+            const bool clo = OPZ && p <= 0, chi = OPZ && p >= nz - 1;
             const T *Qc = sQ[s1];
             const T *Qb = sQ[s0];
             const T *Qlo = clo ? sQ[s1] : sQ[s2];
@@ -654,7 +659,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                                           c2_m1 + c2_c, av(Qb[q + cyp]) + av(qyp_),
                                           av(Qb[q + cym]) + av(qym_), eps, d_m1 + d_c);
             }
-            if (OPEN && (t <= 0 || t >= nz)) v3 = T(0);
+            if (OPZ && (t <= 0 || t >= nz)) v3 = T(0);
             if (NONOS) {
                 // ---- S4 bounds at plane p
                 if constexpr (kPass) {
@@ -719,7 +724,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             }
             if (zero_v1) vt1 = T(0);
             if (zero_v2) vt2 = T(0);
-            if (OPEN && (t - 1 <= 0 || t - 1 >= nz)) vt3 = T(0);
+            if (OPZ && (t - 1 <= 0 || t - 1 >= nz)) vt3 = T(0);
             if constexpr (kOuts) {
                 // the limited velocity of the segment's planes and of its
                 // z-faces (face nz from the segment that ends there)
@@ -814,6 +819,16 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     }
 }
 
+
+// True when the region of tile (tx, ty) and the ring around it lie inside
+// the x-y domain with a cell to spare on every side: no lane reads past an
+// edge, sits on a boundary face or needs a redirected neighbour, so an open
+// grid's tile can take the periodic addressing there.
+template <int RX, int RY> __device__ __forceinline__ bool xy_interior(int tx, int ty, int nx, int ny)
+{
+    constexpr int TX = RX - 4, TY = RY - 4;
+    return tx * TX >= 3 && tx * TX + RX <= nx + 1 && ty * TY >= 3 && ty * TY + RY <= ny + 1;
+}
 
 // Every LDS plane starts at zero, so values computed from not-yet-written
 // slots in the first iterations of a march stay finite (they never reach an

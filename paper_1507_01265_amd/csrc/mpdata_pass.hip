@@ -42,8 +42,19 @@ __global__ __launch_bounds__(RX * RY) void pass_kernel(const GridDesc<T> *__rest
     const int b = wg_begin[blockIdx.x], e = wg_begin[blockIdx.x + 1];
     for (int s = b; s < e; ++s) {
         const Segment sg = segs[s];
-        march<T, RX, RY, OPEN, NONOS, VSIGN, DIV, MODE>(grids[sg.grid], io[sg.grid], 0, sg.tx,
-                                                        sg.ty, sg.z0, sg.z1, eps, sm);
+        const GridDesc<T> &g = grids[sg.grid];
+        if constexpr (OPEN) {
+            // open grid: interior tiles take the periodic x-y addressing
+            if (xy_interior<RX, RY>(sg.tx, sg.ty, g.nx, g.ny))
+                march<T, RX, RY, false, true, NONOS, VSIGN, DIV, MODE>(
+                    g, io[sg.grid], 0, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+            else
+                march<T, RX, RY, true, true, NONOS, VSIGN, DIV, MODE>(
+                    g, io[sg.grid], 0, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+        } else {
+            march<T, RX, RY, false, false, NONOS, VSIGN, DIV, MODE>(
+                g, io[sg.grid], 0, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+        }
         __syncthreads();
     }
 }

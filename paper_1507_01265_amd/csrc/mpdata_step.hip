@@ -27,8 +27,19 @@ __global__ __launch_bounds__(RX * RY) void step_kernel(const GridDesc<T> *__rest
     for (int s = b; s < e; ++s) {
         const Segment sg = segs[s];
         const long long t_start = seg_ticks ? (long long)wall_clock64() : 0;
-        march<T, RX, RY, OPEN, NONOS, VSIGN, DIV, kModeStep>(grids[sg.grid], PassIO<T>{}, flip,
-                                                             sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+        const GridDesc<T> &g = grids[sg.grid];
+        if constexpr (OPEN) {
+            // open grid: interior tiles take the periodic x-y addressing
+            if (xy_interior<RX, RY>(sg.tx, sg.ty, g.nx, g.ny))
+                march<T, RX, RY, false, true, NONOS, VSIGN, DIV, kModeStep>(
+                    g, PassIO<T>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+            else
+                march<T, RX, RY, true, true, NONOS, VSIGN, DIV, kModeStep>(
+                    g, PassIO<T>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+        } else {
+            march<T, RX, RY, false, false, NONOS, VSIGN, DIV, kModeStep>(
+                g, PassIO<T>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+        }
         __syncthreads();
         // optional per-segment duration (workgroup-uniform; one lane stores)
         if (seg_ticks && threadIdx.x == 0) seg_ticks[s] = (long long)wall_clock64() - t_start;

@@ -349,3 +349,32 @@ def test_negative_field_parity_fp32(orc):
     want = oracle_run(orc, f.as_f64(), n, nonos=False)
     got = gpu_run(f, n, dtype=torch.float32, nonos=False)
     assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
+
+
+def _interior_tiles(shape, rx, ry):
+    """Tiles of an open grid whose region and ring lie inside the x-y domain
+    with a cell to spare (they run the periodic x-y addressing)."""
+    nz, ny, nx = shape
+    tx_n, ty_n = (nx + rx - 5) // (rx - 4), (ny + ry - 5) // (ry - 4)
+    return sum(1 for tx in range(tx_n) for ty in range(ty_n)
+               if tx * (rx - 4) >= 3 and tx * (rx - 4) + rx <= nx + 1
+               and ty * (ry - 4) >= 3 and ty * (ry - 4) + ry <= ny + 1)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_open_grid_interior_and_edge_tiles(orc, dtype):
+    """130x100x9 open grid: interior tiles (periodic x-y addressing) and edge
+    tiles (clamped addressing, redirected neighbours) side by side in the
+    default launch shape of each precision."""
+    shape = (9, 100, 130)
+    f = inputs.random_smooth(38, shape, bc=1, cmax=0.15)
+    rx, ry = (32, 24) if dtype == "fp64" else (32, 32)
+    assert _interior_tiles(shape, rx, ry) >= 2
+    if dtype == "fp64":
+        want = oracle_run(orc, f, 4)
+        assert rel_linf(gpu_run(f, 4), want) <= 1e-12
+    else:
+        f = f.astype(np.float32)
+        want = oracle_run(orc, f.as_f64(), 4)
+        got = gpu_run(f, 4, dtype=torch.float32)
+        assert rel_linf(got, want) <= 2e-6 * 4 and rel_l2(got, want) <= 5e-7 * 4
