@@ -171,14 +171,22 @@ __device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi
     }
 }
 
-// Limited pseudo-velocity; the factors are in limiter precision (double)
-// and already capped at 1 (min(1, a, b) = min(min(1, a), min(1, b)) exactly).
+// Limiter factors as stored between the stages: computed in limiter
+// precision (double) and capped at 1, then kept in double for FP64 grids and
+// rounded to float for FP32 grids.  The FP32 variant multiplies V by the
+// factor in FP32, and rounding is monotone, so min(float(a), float(b)) is
+// float(min(a, b)) exactly: taking the minimum after the rounding changes no
+// bit, and the factors travel through LDS and registers at half the size.
+template <typename T> using Factor = std::conditional_t<sizeof(T) == 8, double, float>;
+
+// Limited pseudo-velocity; the factors are already capped at 1
+// (min(1, a, b) = min(min(1, a), min(1, b)) exactly).
 // min(1, f_p) pos(V) + min(1, f_n) neg(V) is the factor of V's own sign
 // times V (the other product is an exact zero).
-template <typename T>
-__device__ __forceinline__ T limited(T v, double bup_a, double bdn_a, double bup_b, double bdn_b)
+template <typename T, typename F>
+__device__ __forceinline__ T limited(T v, F bup_a, F bdn_a, F bup_b, F bdn_b)
 {
-    const double c = v > T(0) ? fmin(bdn_a, bup_b) : fmin(bup_a, bdn_b);
+    const F c = v > T(0) ? fmin(bdn_a, bup_b) : fmin(bup_a, bdn_b);
     return T(c) * v;
 }
 
@@ -291,7 +299,7 @@ template <typename T, int RX, int RY, int MODE, bool DIVP = false> struct Smem {
     // exchanged between lanes (FP32)
     static constexpr int PX1 = sizeof(T) == 8 ? 1 : PP;
     T sFA1[PX1], sFA2[PP];               // antidiffusive donor fluxes, lower faces
-    double sBU[PP], sBD[PP];             // limiter factors, plane t-2
+    Factor<T> sBU[PP], sBD[PP];          // limiter factors, plane t-2
     T sFC1[PX1], sFC2[PP];               // corrective fluxes, lower faces
 };
 
@@ -319,7 +327,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     T *__restrict__ sC1 = sm.sC1, *__restrict__ sC2 = sm.sC2, *__restrict__ sC3 = sm.sC3;
     T *__restrict__ sH = sm.sH, *__restrict__ sFA1 = sm.sFA1, *__restrict__ sFA2 = sm.sFA2;
     T *__restrict__ sD = sm.sD;
-    L *__restrict__ sBU = sm.sBU, *__restrict__ sBD = sm.sBD;
+    using F = Factor<T>;
+    F *__restrict__ sBU = sm.sBU, *__restrict__ sBD = sm.sBD;
     T *__restrict__ sFC1 = sm.sFC1, *__restrict__ sFC2 = sm.sFC2;
 
     const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -480,7 +489,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     T r_d_m1 = T(0);  // divergence of the column's cell at plane t-1 (DIV)
     T v1_m2 = T(0), v2_m2 = T(0), v3_m1 = T(0); // V at plane t-2, V3 at face t-1
     T fa3_m1 = T(0);                            // antidiffusive flux, face t-1
-    L bu_m2 = 1.0, bd_m2 = 1.0;                 // limiter factors (capped at 1), plane t-2
+    F bu_m2 = F(1), bd_m2 = F(1);               // limiter factors (capped at 1), plane t-2
     T fc3_m2 = T(0), fc3_m3 = T(0);             // corrective flux, faces t-2, t-3
     T fc1_m3 = T(0), fc2_m3 = T(0);             // corrective fluxes, lower x/y faces of plane t-3
 
@@ -689,7 +698,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         }
         __syncthreads();  // (F) antidiffusive fluxes visible
 
-        L bu_m1 = 1.0, bd_m1 = 1.0;
+        F bu_m1 = F(1), bd_m1 = F(1);
         if (NONOS) {
             // ---- S5 limiter factors at plane t-1
             T fa1_hi;
@@ -704,8 +713,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             // over the common denominator (IN + eps)(OUT + eps)
             const L din = in + eps_l, dou = ou + eps_l;
             const L r = rcp_nr(din * dou) * L(h_m1);
-            bu_m1 = fmin(L(1), ((L(mx) - L(p1_m1)) * dou) * r);
-            bd_m1 = fmin(L(1), ((L(p1_m1) - L(mn)) * din) * r);
+            bu_m1 = F(fmin(L(1), ((L(mx) - L(p1_m1)) * dou) * r));
+            bd_m1 = F(fmin(L(1), ((L(p1_m1) - L(mn)) * din) * r));
         }
 
         T fc1_r, fc2_r, fc3_m1;
@@ -715,7 +724,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             const T *Qr = sQ[s2];
             T vt1 = v1_m2, vt2 = v2_m2, vt3 = v3_m1;
             if (NONOS) {
-                L bu_a, bd_a;
+                F bu_a, bd_a;
                 if constexpr (kDpp) bu_a = from_lo(bu_m2), bd_a = from_lo(bd_m2);
                 else bu_a = sBU[q + XM], bd_a = sBD[q + XM];
                 vt1 = limited(v1_m2, bu_a, bd_a, bu_m2, bd_m2);
@@ -845,7 +854,7 @@ __device__ __forceinline__ void smem_clear(Smem<T, RX, RY, MODE, DIVP> &sm)
         sm.sC1[i] = sm.sC2[i] = sm.sC3[i] = sm.sH[i] = T(0);
         sm.sFA2[i] = sm.sFC2[i] = T(0);
         if (i < S::PX1) sm.sFA1[i] = sm.sFC1[i] = T(0);
-        sm.sBU[i] = sm.sBD[i] = 1.0;
+        sm.sBU[i] = sm.sBD[i] = Factor<T>(1);
     }
     __syncthreads();
 }
