@@ -126,9 +126,10 @@ int mpdata_create(const mpdata_params *p, void *psi, const void *u1, const void 
  * the state after the steps (an odd step count ends with one device copy
  * from the workspace into psi).  Each step is one launch of the persistent
  * fused kernel over a plan of (tile, z-range) segments balanced across the
- * GPU (iord 2; runs of steps are replayed from a hipGraph built on first
- * use), or a chain of iord - 1 launches of it over the same plan (iord > 2:
- * the fused step, then one launch per further corrective pass). */
+ * GPU (iord 2), or a chain of iord - 1 launches of it over the same plan
+ * (iord > 2: the fused step, then one launch per further corrective pass).
+ * Runs of 8 steps are replayed from a hipGraph built on first use (unless
+ * MPDATA_FLAG_NO_GRAPH). */
 int mpdata_step(mpdata_ctx *ctx, int32_t nsteps);
 
 /* Mass M = sum over cells of h*psi with a compensated (double-double)

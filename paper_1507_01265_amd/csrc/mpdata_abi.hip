@@ -429,7 +429,9 @@ static hipError_t launch_one(Engine &e, int flip, long long *ticks)
                                           ticks, e.stream);
 }
 
-// Graph of kGraphSteps step launches (each reading what the previous wrote).
+// Graph of kGraphSteps steps (each launch reading what the previous wrote):
+// one step launch per step, or the chain of corrective passes of each step
+// (iord > 2).
 static hipError_t build_graph(Engine &e)
 {
     hipError_t r = hipGraphCreate(&e.graph_def, 0);
@@ -440,6 +442,32 @@ static hipError_t build_graph(Engine &e)
     const void *segp = e.ws + e.lay.segs;
     const void *wgp = e.ws + e.lay.wg;
     long long *no_ticks = nullptr;
+    if (e.iord > 2) {
+        const int npass = e.iord - 1;
+        std::vector<const void *> gds((size_t)kGraphSteps * npass), ios((size_t)kGraphSteps * npass);
+        for (int s = 0; s < kGraphSteps; ++s)
+            for (int j = 0; j < npass; ++j) {
+                const int mode = j == 0 ? mpd::kPassHead : (j == npass - 1 ? mpd::kPassLast : mpd::kPassMid);
+                const size_t i = (size_t)(s & 1) * npass + j, n = (size_t)s * npass + j;
+                gds[n] = (const mpd::GridDesc<double> *)(e.ws + e.lay.pass_grids) + i;
+                ios[n] = (const mpd::PassIO<double> *)(e.ws + e.lay.pass_io) + i;
+                void *args[] = {(void *)&gds[n], (void *)&ios[n], (void *)&segp, (void *)&wgp,
+                                (void *)&e.eps};
+                hipKernelNodeParams kp{};
+                kp.func = (void *)(e.dtype == MPDATA_FP32 ? mpd::pass_kernel_ptr<float>(e.tile, e.variant, mode)
+                                                          : mpd::pass_kernel_ptr<double>(e.tile, e.variant, mode));
+                kp.gridDim = dim3(e.nwg);
+                kp.blockDim = dim3(sh.rx * sh.ry);
+                kp.sharedMemBytes = 0;
+                kp.kernelParams = args;
+                kp.extra = nullptr;
+                hipGraphNode_t node;
+                r = hipGraphAddKernelNode(&node, e.graph_def, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+                if (r != hipSuccess) return r;
+                prev = node;
+            }
+        return hipGraphInstantiate(&e.graph, e.graph_def, nullptr, nullptr, 0);
+    }
     int flips[kGraphSteps];
     for (int s = 0; s < kGraphSteps; ++s) {
         flips[s] = s & 1;
@@ -466,7 +494,7 @@ static int engine_step(Engine &e, int32_t nsteps)
     if (nsteps < 0) return fail_to(e.err, MPDATA_EINVAL, "nsteps must be >= 0");
     hipError_t r = hipSuccess;
     int32_t done = 0;
-    if (e.use_graph && e.iord == 2 && nsteps >= kGraphSteps) {
+    if (e.use_graph && e.iord >= 2 && nsteps >= kGraphSteps) {
         if (!e.graph) {
             r = build_graph(e);
             if (r != hipSuccess) {

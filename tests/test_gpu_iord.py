@@ -137,3 +137,13 @@ def test_full_size_rotation_fp64(orc):
     got = gpu_run(f, 2, iord=3)
     assert rel_linf(got, want) <= 1e-12
     assert got.min() >= -1e-15
+
+
+@pytest.mark.parametrize("iord", [3, 4])
+def test_graph_and_plain_launches_agree(iord):
+    """19 steps: two replays of the 8-step graph of pass chains plus three
+    plain steps, against 19 plain steps -- bit for bit."""
+    f = inputs.random_smooth(208, (13, 45, 70), cmax=0.15)
+    a = gpu_run(f, 19, iord=iord)
+    b = gpu_run(f, 19, iord=iord, graph=False)
+    np.testing.assert_array_equal(a, b)
