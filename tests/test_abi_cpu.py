@@ -147,3 +147,11 @@ def test_option_tiles_are_the_default_shapes():
     for tile in range(1, _lib.mpdata_tile_count() + 1):
         ok = _lib.mpdata_workspace_bytes(_params(flags=_lib.MPDATA_FLAG_DIV, tile=tile)) > 0
         assert ok == (tile in t)
+
+
+def test_batches_run_the_iord_2_step_only():
+    """A batch is one launch of the fused step per step: more corrective
+    passes are for single-grid contexts."""
+    ok = _lib.mpdata_batch_workspace_bytes([_params(), _params(nx=20)], 0, 0)
+    assert ok > 0
+    assert _lib.mpdata_batch_workspace_bytes([_params(iord=3), _params(nx=20, iord=3)], 0, 0) == 0
