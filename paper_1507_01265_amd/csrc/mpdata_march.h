@@ -285,6 +285,9 @@ enum { kModeStep = 0, kModeHead = 1, kModeMid = 2, kModeLast = 3 };
 // LDS planes of one workgroup (each padded by one cell on every side).
 template <typename T, int RX, int RY, int MODE, bool DIVP = false> struct Smem {
     static constexpr int PX = RX + 2, PP = PX * (RY + 2);
+    // planes read only by x-neighbours go through LDS only where
+    // x-neighbours are not exchanged between lanes (FP32)
+    static constexpr int PX1 = sizeof(T) == 8 ? 1 : PP;
     // kModeStep/kModeHead: psi^n plane t (its ring holds real data);
     // kModeMid/kModeLast: the running upper bound of plane t, with the lower
     // bound in sPm
@@ -292,12 +295,11 @@ template <typename T, int RX, int RY, int MODE, bool DIVP = false> struct Smem {
     static constexpr int PM = MODE >= kModeMid ? PP : 1;
     T sPm[PM];
     T sQ[3][PP];                         // psi1, planes t-2 .. t in fixed slots
-    T sC1[PP], sC2[PP], sC3[PP], sH[PP]; // Courant column sums, h: plane t-1
+    // Courant column sums and h of plane t-1; the y-sums serve only the
+    // x-neighbours, which FP64 exchanges between lanes
+    T sC1[PP], sC2[PX1], sC3[PP], sH[PP];
     static constexpr int PD = DIVP ? PP : 1;
     T sD[PD];                            // cell divergence of the velocity field: plane t-1
-    // x-face fluxes go through LDS only where x-neighbours are not
-    // exchanged between lanes (FP32)
-    static constexpr int PX1 = sizeof(T) == 8 ? 1 : PP;
     T sFA1[PX1], sFA2[PP];               // antidiffusive donor fluxes, lower faces
     Factor<T> sBU[PP], sBD[PP];          // limiter factors, plane t-2
     T sFC1[PX1], sFC2[PP];               // corrective fluxes, lower faces
@@ -755,7 +757,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         // sums/h of plane t for the next iteration: the reads of plane t-1
         // happened before (F)
         sC1[q] = c1_c;
-        sC2[q] = c2_c;
+        if constexpr (!kDpp) sC2[q] = c2_c;
         sC3[q] = c3_c;
         sH[q] = curA.h;
         if constexpr (DIV) sD[q] = d_c;
@@ -851,7 +853,8 @@ __device__ __forceinline__ void smem_clear(Smem<T, RX, RY, MODE, DIVP> &sm)
         if (i < S::PM) sm.sPm[i] = T(0);
         if (i < S::PD) sm.sD[i] = T(0);
         sm.sQ[0][i] = sm.sQ[1][i] = sm.sQ[2][i] = T(0);
-        sm.sC1[i] = sm.sC2[i] = sm.sC3[i] = sm.sH[i] = T(0);
+        sm.sC1[i] = sm.sC3[i] = sm.sH[i] = T(0);
+        if (i < S::PX1) sm.sC2[i] = T(0);
         sm.sFA2[i] = sm.sFC2[i] = T(0);
         if (i < S::PX1) sm.sFA1[i] = sm.sFC1[i] = T(0);
         sm.sBU[i] = sm.sBD[i] = Factor<T>(1);
