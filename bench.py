@@ -138,17 +138,34 @@ def time_gpu(fields, dtype_tag, steps, warmup, tile=0, iord=2, div=False):
     if warmup:
         s.step(warmup)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    s.step(steps)
-    stop.record(stream)
+    # the timed region is exactly `steps` steps; events between chunks of 8
+    # (one replayed graph each) give per-chunk times for the spread
+    chunks = [8] * (steps // 8) + ([steps % 8] if steps % 8 else [])
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(len(chunks) + 1)]
+    events[0].record(stream)
+    for c, ev in zip(chunks, events[1:]):
+        s.step(c)
+        ev.record(stream)
     torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
+    ms = events[0].elapsed_time(events[-1])
+    per_step = [events[i].elapsed_time(events[i + 1]) / c for i, c in enumerate(chunks) if c == 8]
     m1 = s.mass()
     psi_min = float(s.psi.min().item())
     s.close()
-    return {"ms": ms, "mass0": m0, "mass1": m1, "psi_min": psi_min}
+    return {"ms": ms, "mass0": m0, "mass1": m1, "psi_min": psi_min, "per_step_ms": per_step}
+
+
+def spread(samples):
+    """Median and 95 % Student-t half-width of the mean of per-chunk step
+    times (None with fewer than two samples)."""
+    import numpy as np
+    from scipy import stats
+    x = np.asarray(samples, dtype=float)
+    if x.size < 2:
+        return None
+    half = float(stats.t.ppf(0.975, x.size - 1) * x.std(ddof=1) / np.sqrt(x.size))
+    return {"median_ms": float(np.median(x)), "mean_ms": float(x.mean()), "ci95_half_ms": half,
+            "ci95_rel": half / float(x.mean()), "chunks_of_8_steps": int(x.size)}
 
 
 def cpu_baseline(fields, budget_s=12.0, max_steps=40, iord=2, div=False):
@@ -406,6 +423,7 @@ def main():
                       "bytes_per_step_by_design": chain_bytes(fields.shape, word, iord),
                       "achieved_by_design_GBs": chain_bytes(fields.shape, word, iord)
                       / (ms_per_step / 1e3) / 1e9}} if iord > 2 else {}),
+        "step_time_spread": spread(g["per_step_ms"]),
         "mass_drift": (g["mass1"] - g["mass0"]) / g["mass0"],
         "psi_min": g["psi_min"],
     }
