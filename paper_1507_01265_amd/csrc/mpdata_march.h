@@ -573,6 +573,13 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         __syncthreads();  // (D) psi1(t) and the limiter factors of t-2 are visible
 
         T v1, v2, v3, fa1 = T(0), fa2 = T(0), fa3_c = T(0);
+        // FP32: the LDS operands of S6 at plane t-2 (psi1 and the limiter
+        // factors of the x- and y-neighbours), written before (D), are read
+        // during the arithmetic of this phase instead of after (F) (1.6 %
+        // faster FP32 step, measured; FP64, at its register limit, keeps them
+        // after (F))
+        T q6_y = T(0), q6_x = T(0);
+        F bu6_y = F(1), bd6_y = F(1), bu6_x = F(1), bd6_x = F(1);
         T pc_xlo = T(0), p2_xm = T(0);
         T mx = T(0), mn = T(0);
         {
@@ -654,6 +661,18 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                 if (zero_v2) v2 = T(0);
             }
             __builtin_amdgcn_sched_barrier(0);
+            if constexpr (!kDpp) {
+                q6_y = sQ[s2][q + YM];
+                if (NONOS) {
+                    bu6_y = sBU[q + YM];
+                    bd6_y = sBD[q + YM];
+                }
+                q6_x = sQ[s2][q + XM];
+                if (NONOS) {
+                    bu6_x = sBU[q + XM];
+                    bd6_x = sBD[q + XM];
+                }
+            }
             {
                 // z-face t between a = plane t-1 and b = plane t; transverse x then y
                 T pc_xp, pc_xm;
@@ -723,14 +742,14 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         {
             // ---- S6 + corrective fluxes at plane r = t-2 (lower faces) and on face t-1;
             // the y-fluxes of t-3 in sFC2 were read before (D)
-            const T *Qr = sQ[s2];
             T vt1 = v1_m2, vt2 = v2_m2, vt3 = v3_m1;
             if (NONOS) {
                 F bu_a, bd_a;
                 if constexpr (kDpp) bu_a = from_lo(bu_m2), bd_a = from_lo(bd_m2);
-                else bu_a = sBU[q + XM], bd_a = sBD[q + XM];
+                else bu_a = bu6_x, bd_a = bd6_x;
                 vt1 = limited(v1_m2, bu_a, bd_a, bu_m2, bd_m2);
-                vt2 = limited(v2_m2, sBU[q + YM], sBD[q + YM], bu_m2, bd_m2);
+                if constexpr (kDpp) bu6_y = sBU[q + YM], bd6_y = sBD[q + YM];
+                vt2 = limited(v2_m2, bu6_y, bd6_y, bu_m2, bd_m2);
                 vt3 = limited(v3_m1, bu_m2, bd_m2, bu_m1, bd_m1);
             }
             if (zero_v1) vt1 = T(0);
@@ -747,9 +766,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                 if (is_out && ((f >= z0 && f < z1) || (f == nz && z1 == nz)))
                     bstore<T>(plane_rsrc<T>(io.w3, f, pc_cells), b_c, vt3);
             }
-            if constexpr (!kDpp) p2_xm = Qr[q + XM];
+            if constexpr (!kDpp) p2_xm = q6_x;
             fc1_r = donor(p2_xm, p1_m2, vt1);
-            fc2_r = donor(Qr[q + YM], p1_m2, vt2);
+            if constexpr (kDpp) q6_y = sQ[s2][q + YM];
+            fc2_r = donor(q6_y, p1_m2, vt2);
             if constexpr (!kDpp) sFC1[q] = fc1_r;
             sFC2[q] = fc2_r;
             fc3_m1 = donor(p1_m2, p1_m1, vt3);
