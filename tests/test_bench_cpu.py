@@ -1,0 +1,74 @@
+"""bench.py's host-side contract: the one-GPU rule, the byte accounting
+behind the roofline, the timing spread and the traffic lookup."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "single" in r.stderr and "GPU" in r.stderr
+
+
+def test_algorithmic_bytes_are_five_reads_and_one_write():
+    """psi, h and the new psi are nx*ny*nz words; u1, u2, u3 carry one more
+    face along their own axis: 48.2 B per FP64 cell on the benchmark grid."""
+    nz, ny, nx = 64, 256, 512
+    want = 8 * (3 * nx * ny * nz + (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1))
+    assert bench.algorithmic_bytes((nz, ny, nx), 8) == want == 404094976
+    assert bench.algorithmic_bytes((nz, ny, nx), 4) * 2 == want
+    assert abs(want / (nx * ny * nz) - 48.2) < 0.05
+
+
+def test_chain_bytes_by_design():
+    """iord 3 = head (5 in, psi out, 3 velocity faces, 2 bound arrays) + last
+    (iterate, h, 2 bounds and 3 velocity faces in, psi out)."""
+    nz, ny, nx = 4, 5, 6
+    n = nx * ny * nz
+    faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+    head = (3 * n + faces) + faces + 2 * n
+    last = 4 * n + faces + n
+    assert bench.chain_bytes((nz, ny, nx), 8, 3) == 8 * (head + last)
+    mid = 4 * n + faces + 3 * n + faces
+    assert bench.chain_bytes((nz, ny, nx), 8, 5) == 8 * (head + 2 * mid + last)
+    assert bench.chain_bytes((nz, ny, nx), 8, 3, nonos=False) < bench.chain_bytes((nz, ny, nx), 8, 3)
+
+
+def test_timing_spread():
+    assert bench.spread([0.2]) is None
+    s = bench.spread([0.25, 0.25, 0.25])
+    assert s["median_ms"] == 0.25 and s["ci95_half_ms"] == 0.0
+    s = bench.spread([1.0, 2.0, 3.0, 4.0])
+    assert s["median_ms"] == 2.5 and s["mean_ms"] == 2.5 and s["chunks_of_8_steps"] == 4
+    # t(0.975, 3) = 3.1824..., sample std of 1..4 = 1.2910..., sqrt(4) = 2
+    assert abs(s["ci95_half_ms"] - 3.182446 * 1.290994 / 2) < 1e-5
+
+
+def test_traffic_needs_the_current_kernel_source(tmp_path, monkeypatch):
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1507_01265_amd", "csrc")
+    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                  for f in ("mpdata_march.h", "mpdata_step.hip"))).hexdigest()
+    good = tmp_path / "good.md"
+    good.write_text(f"kernel_source_sha256: {sha}\ntraffic_bytes_per_launch: 12345\n")
+    stale = tmp_path / "stale.md"
+    stale.write_text("kernel_source_sha256: 0000\ntraffic_bytes_per_launch: 12345\n")
+    monkeypatch.setattr(bench, "PROFILES", {"good": str(good), "stale": str(stale)})
+    assert bench.measured_traffic("good") == 12345.0
+    assert bench.measured_traffic("stale") is None
+    assert bench.measured_traffic("missing") is None
+
+
+def test_committed_profiles_match_the_kernel():
+    """The committed counter summaries were taken with the current step
+    kernel source, so the benchmark line reports measured traffic."""
+    for w in ("rotation-fp64", "rotation-fp32", "streamfunction-fp32"):
+        assert bench.measured_traffic(w) is not None, w
