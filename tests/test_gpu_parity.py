@@ -365,16 +365,21 @@ def _interior_tiles(shape, rx, ry):
 def test_open_grid_interior_and_edge_tiles(orc, dtype):
     """130x100x9 open grid: interior tiles (periodic x-y addressing) and edge
     tiles (clamped addressing, redirected neighbours) side by side in the
-    default launch shape of each precision."""
+    default launch shape of each precision, with each option."""
     shape = (9, 100, 130)
     f = inputs.random_smooth(38, shape, bc=1, cmax=0.15)
     rx, ry = (32, 24) if dtype == "fp64" else (32, 32)
     assert _interior_tiles(shape, rx, ry) >= 2
-    if dtype == "fp64":
-        want = oracle_run(orc, f, 4)
-        assert rel_linf(gpu_run(f, 4), want) <= 1e-12
-    else:
-        f = f.astype(np.float32)
-        want = oracle_run(orc, f.as_f64(), 4)
-        got = gpu_run(f, 4, dtype=torch.float32)
-        assert rel_linf(got, want) <= 2e-6 * 4 and rel_l2(got, want) <= 5e-7 * 4
+    # plain, with the divergent-flow term, and with the variable-sign option
+    # on a field that crosses zero
+    cases = [(f, 4, {}), (f, 2, {"div": True}), (_mixed_sign(39, shape, 1), 2, {"vsign": True})]
+    for g, n, opts in cases:
+        print(f"{dtype} {opts}", flush=True)
+        if dtype == "fp64":
+            want = oracle_run(orc, g, n, **opts)
+            assert rel_linf(gpu_run(g, n, **opts), want) <= 1e-12
+        else:
+            g = g.astype(np.float32)
+            want = oracle_run(orc, g.as_f64(), n, **opts)
+            got = gpu_run(g, n, dtype=torch.float32, **opts)
+            assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
