@@ -309,6 +309,21 @@ def test_full_size_rotation_fp64_100_steps(orc):
 
 
 @pytest.mark.slow
+def test_full_size_rotation_fp32_100_steps(orc):
+    """512x256x64 rotation in FP32 + FP64 limiter, the benchmark's 100 steps,
+    against the FP64 oracle within the per-step FP32 allowance; the zero
+    background stays non-negative."""
+    f = inputs.rotation().astype(np.float32)
+    n = 100
+    want = oracle_run(orc, f.as_f64(), n)
+    got = gpu_run(f, n, dtype=torch.float32)
+    print(f"rel-Linf {rel_linf(got, want):.3e} rel-L2 {rel_l2(got, want):.3e} min {got.min():.3e}",
+          flush=True)
+    assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
+    assert got.min() >= 0.0
+
+
+@pytest.mark.slow
 def test_full_size_streamfunction_fp64(orc):
     """1024x512x64 open domain in FP64 (the open FP64 kernel), 2 steps."""
     f = inputs.streamfunction()
