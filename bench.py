@@ -168,6 +168,18 @@ def spread(samples):
             "ci95_rel": half / float(x.mean()), "chunks_of_8_steps": int(x.size)}
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(fields, budget_s=12.0, max_steps=40, iord=2, div=False):
     """The FP64 oracle as it stands, stepped on the host until the budget is
     spent (at least 2 steps)."""
@@ -331,6 +343,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="launch shape id (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads for the CPU baseline (0 = the OpenMP default)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="served: seconds of arrivals")
     ap.add_argument("--budget", type=float, default=200e9, help="served: HBM budget in bytes")
@@ -429,13 +443,16 @@ def main():
     }
     if not args.no_cpu_baseline:
         import oracle
+        if args.cpu_threads:
+            oracle.set_threads(args.cpu_threads)
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         f64 = fields if dtag == "f64" else fields.astype("float32").as_f64()
         steps, el = cpu_baseline(f64, args.cpu_budget, iord=iord, div=div)
         line["cpu_baseline"] = {"value": cells * steps / el, "unit": "cell-updates/s",
                                 "cores": oracle.threads(), "kind": "oracle",
                                 "sample": f"{nx}x{ny}x{nz} {args.workload} inputs, {steps} FP64 "
-                                          f"steps of the whole grid, {el:.1f} s"}
+                                          f"steps of the whole grid, {el:.1f} s",
+                                "cpu_model": cpu_model()}
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

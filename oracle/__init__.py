@@ -78,6 +78,8 @@ def _load():
         lib.orc_open_inflow.restype = ctypes.c_double
         lib.orc_threads.argtypes = []
         lib.orc_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -171,3 +173,11 @@ def open_inflow(psi, u1, u2, u3):
 def threads() -> int:
     """OpenMP threads the oracle's stage loops use."""
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> int:
+    """Runs the stage loops on n OpenMP threads (results do not depend on
+    it); returns the number now in effect."""
+    if n < 1:
+        raise ValueError("threads must be >= 1")
+    return int(_load().orc_set_threads(int(n)))

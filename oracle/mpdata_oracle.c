@@ -592,3 +592,15 @@ int orc_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the number of OpenMP threads of the stage loops (n >= 1; ignored
+ * without OpenMP); returns the number now in effect. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return orc_threads();
+}

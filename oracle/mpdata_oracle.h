@@ -53,8 +53,10 @@ double orc_mass(long n, const double *h, const double *psi);
 double orc_open_inflow(const orc_params *p, const double *psi, const double *u1,
                        const double *u2, const double *u3);
 
-/* Threads used by the stage loops. */
+/* Threads used by the stage loops, and setting them (n >= 1; returns the
+ * number now in effect).  No result depends on the thread count. */
 int orc_threads(void);
+int orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

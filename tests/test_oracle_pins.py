@@ -639,3 +639,21 @@ def test_divergence_term_conserves_mass(orc):
     out = orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 5, div=True, iord=3)
     assert abs(orc.mass(out, f.h) - m0) / m0 < 1e-13
     assert not np.array_equal(out, orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 5, iord=3))
+
+
+def test_results_do_not_depend_on_the_thread_count(orc):
+    """Every output element is computed by one thread from inputs no thread
+    writes, so one thread and several give the same bits (the CPU baseline
+    may be timed on any number of cores)."""
+    f = inputs.random_smooth(61, (6, 20, 24), bc=1, cmax=0.3)
+    before = orc.threads()
+    try:
+        assert orc.set_threads(1) == 1
+        one = orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 3, bc=f.bc, iord=3, div=True)
+        orc.set_threads(max(2, before))
+        many = orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 3, bc=f.bc, iord=3, div=True)
+    finally:
+        orc.set_threads(before)
+    np.testing.assert_array_equal(one, many)
+    with pytest.raises(ValueError):
+        orc.set_threads(0)
