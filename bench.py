@@ -75,15 +75,16 @@ OPTIONS = {"rotation-fp64-iord3": {"iord": 3}, "rotation-fp32-iord3": {"iord": 3
 
 def chain_bytes(shape, word, iord, nonos=True):
     """Bytes a step of iord > 2 moves by design: the fused step also writes
-    its limited velocity (3 face arrays) and, with the limiter, two running
-    bound arrays; each further pass reads its iterate, velocity, h and the
-    bounds, and writes the next iterate, velocity and bounds (the last pass
+    its limited velocity (3 face arrays) and, with the limiter, psi1; each
+    further pass reads its iterate, velocity, h and two bound arrays (psi1
+    and psi^n after the fused step, the running bounds after that), and
+    writes the next iterate, velocity and running bounds (the last pass
     writes psi only)."""
     nz, ny, nx = shape
     n = nx * ny * nz
     faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
     b = 2 if nonos else 0
-    head = 3 * n + faces + faces + b * n
+    head = 3 * n + faces + faces + (b // 2) * n
     mid = (2 + b) * n + faces + (1 + b) * n + faces
     last = (2 + b) * n + faces + n
     return word * (head + (iord - 3) * mid + last)

@@ -104,8 +104,9 @@ typedef struct mpdata_ctx mpdata_ctx; /* opaque */
 /* Bytes of workspace mpdata_create() needs for these parameters (0 if they
  * are invalid).  The workspace holds the second psi buffer of the time loop
  * and the mass-reduction partials; with iord > 2 also the intermediate
- * iterates, the limited velocities (face arrays) and, with the limiter, the
- * running bounds of the corrective passes (one set; two from iord 4 on). */
+ * iterates, the limited velocities (face arrays) and, with the limiter, psi1
+ * of the first pass and the running bounds of the middle passes (one set;
+ * two from iord 4 on). */
 size_t mpdata_workspace_bytes(const mpdata_params *p);
 
 /* Validates the parameters and arrays and binds them to a new context.

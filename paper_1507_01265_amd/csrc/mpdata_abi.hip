@@ -263,7 +263,7 @@ const char *check_plan(const std::vector<mpdata_params> &grids, int tile,
 struct Layout {
     size_t psi2, grids, segs, wg, ticks, partials, result, flags;
     // a single grid with iord > 2: the buffers of the chain of corrective
-    // passes (iterates, limited velocities, running bounds, two sets used in
+    // passes (iterates, limited velocities, psi1 and running bounds, two sets used in
     // turn) and the descriptors of its launches for both step parities
     size_t it[2], w[2][3], bmx[2], bmn[2], pass_grids, pass_io;
     size_t total;
@@ -302,10 +302,15 @@ Layout layout_for(const std::vector<mpdata_params> &grids, int max_segs, int max
                 off += align_up(faces[d] * w);
             }
             if (p.nonos) {
+                // bmx[0] takes psi1 from the head launch; the running bounds
+                // of middle pass j go to set j & 1 (passes 1 .. iord - 3), so
+                // set 1 needs a minimum from iord 4 on, set 0 from iord 5 on
                 l.bmx[s] = off;
                 off += align_up(cells_of(&p) * w);
-                l.bmn[s] = off;
-                off += align_up(cells_of(&p) * w);
+                if (p.iord >= 5 - s) {
+                    l.bmn[s] = off;
+                    off += align_up(cells_of(&p) * w);
+                }
             }
         }
         l.pass_grids = off;
@@ -549,8 +554,10 @@ static int engine_mass(Engine &e, int i, double *out)
 // Descriptors of the chain of corrective passes (iord > 2) for both step
 // parities f: pass j reads psi[f] (j = 0) or iterate set (j-1) mod 2 and
 // writes psi[1-f] (the last pass) or iterate set j mod 2; its velocity field
-// is the Courant numbers (j = 0) or the limited velocity of pass j-1, its
-// running bounds those written by pass j-1.  FP32 reinterprets the pointers.
+// is the Courant numbers (j = 0) or the limited velocity of pass j-1.  Its
+// limiter bounds come from two cell arrays: psi1 (written by the head
+// launch) and psi[f] itself for pass 1, the running bounds written by pass
+// j-1 after that.  FP32 reinterprets the pointers.
 static void pass_descriptors(const Engine &e, std::vector<mpd::GridDesc<double>> &pg,
                              std::vector<mpd::PassIO<double>> &pio)
 {
@@ -569,8 +576,10 @@ static void pass_descriptors(const Engine &e, std::vector<mpd::GridDesc<double>>
                 d.u2 = at(e.lay.w[in][1]);
                 d.u3 = at(e.lay.w[in][2]);
                 if (e.nonos) {
+                    // bounds over max/min(bmx, bmn, iterate): psi1 and psi^n
+                    // after the head launch, the running bounds after a middle one
                     io.bmx = at(e.lay.bmx[in]);
-                    io.bmn = at(e.lay.bmn[in]);
+                    io.bmn = j == 1 ? g.psi[f] : at(e.lay.bmn[in]);
                 }
             }
             d.psi[0] = j == 0 ? g.psi[f] : at(e.lay.it[in]);
@@ -580,8 +589,8 @@ static void pass_descriptors(const Engine &e, std::vector<mpd::GridDesc<double>>
                 io.w2 = at(e.lay.w[out][1]);
                 io.w3 = at(e.lay.w[out][2]);
                 if (e.nonos) {
-                    io.mx = at(e.lay.bmx[out]);
-                    io.mn = at(e.lay.bmn[out]);
+                    io.mx = at(e.lay.bmx[out]);  // the head writes psi1 here
+                    if (j > 0) io.mn = at(e.lay.bmn[out]);
                 }
             }
         }

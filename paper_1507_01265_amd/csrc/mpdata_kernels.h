@@ -15,10 +15,12 @@ template <typename T> struct GridDesc {
 };
 
 // The extra arrays of one launch in a chain of corrective passes (a step
-// with iord > 2): bmx, bmn are the running bounds of the earlier iterates
-// (cell arrays, read by a further pass); w1, w2, w3 the limited
+// with iord > 2): bmx, bmn are two cell arrays whose cell-by-cell max and
+// min with the iterate bound a further pass (psi1 and psi^n after the head
+// launch, the running bounds after a middle one); w1, w2, w3 the limited
 // antidiffusive velocity of the launch (face arrays) and mx, mn its running
-// bounds (cell arrays), both written for the next pass.
+// bounds (cell arrays; the head launch writes psi1 to mx and nothing to mn),
+// both written for the next pass.
 template <typename T> struct PassIO {
     const T *bmx, *bmn;
     T *w1, *w2, *w3, *mx, *mn;

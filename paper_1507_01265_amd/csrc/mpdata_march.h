@@ -264,8 +264,8 @@ template <typename T> struct PlaneA {
     T u1lo, u1hi, u2lo, u2hi, h;
 };
 // ... and psi^n and the Courant number of its lower z-face (needed two
-// iterations ahead; in a further corrective pass also the running bounds
-// bx, bn of the earlier iterates).
+// iterations ahead; in a further corrective pass also the two cell arrays
+// bx, bn that bound the earlier iterates).
 template <typename T> struct PlaneB {
     T pn, u3lo, bx, bn;
 };
@@ -275,11 +275,17 @@ template <typename T> struct PlaneB {
 // What a launch of the march computes.  kModeStep: one time step (the
 // donor-cell pass and one corrective pass).  A step with k > 1 corrective
 // passes (iord = k + 1) runs as a chain of launches: kModeHead is the time
-// step that also writes its limited antidiffusive velocity and the running
-// bounds max/min(psi^n, psi1) cell by cell; kModeMid and kModeLast run one
-// further corrective pass on the previous launch's result, with the previous
-// limited velocity in the place of the Courant numbers and the running bounds
-// in the place of psi^n; kModeMid writes its velocity and running bounds on.
+// step that also writes its limited antidiffusive velocity and psi1;
+// kModeMid and kModeLast run one further corrective pass on the previous
+// launch's result, with the previous limited velocity in the place of the
+// Courant numbers.  Their limiter bounds run over the iterate and two cell
+// arrays bx, bn, taken cell by cell as max(bx, bn, iterate) and
+// min(bx, bn, iterate): psi1 and psi^n (the step's input) after the head
+// launch, the running maximum and minimum after a middle one -- where
+// bx >= bn, so the same expressions carry them on.  The max/min over a set of
+// fields at each of the 7 points equals the 7-point max/min of their
+// cell-by-cell max/min, so two arrays stand for every earlier iterate.
+// kModeMid writes its velocity and the running bounds on.
 enum { kModeStep = 0, kModeHead = 1, kModeMid = 2, kModeLast = 3 };
 
 // LDS planes of one workgroup (each padded by one cell on every side).
@@ -460,10 +466,12 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     T M_c = T(0), m_c = T(0), M_m1 = T(0), m_m1 = T(0);
     if constexpr (kPass && NONOS) {
         const int kp = plane_of(t0 - 1);
-        M_m1 = fmax(bload<T>(plane_rsrc(io.bmx, kp, pc_cells), b_c), pn_prev);
-        m_m1 = fmin(bload<T>(plane_rsrc(io.bmn, kp, pc_cells), b_c), pn_prev);
-        M_c = fmax(cur.bx, cur.pn);
-        m_c = fmin(cur.bn, cur.pn);
+        const T bx_p = bload<T>(plane_rsrc(io.bmx, kp, pc_cells), b_c);
+        const T bn_p = bload<T>(plane_rsrc(io.bmn, kp, pc_cells), b_c);
+        M_m1 = fmax(fmax(bx_p, bn_p), pn_prev);
+        m_m1 = fmin(fmin(bx_p, bn_p), pn_prev);
+        M_c = fmax(fmax(cur.bx, cur.bn), cur.pn);
+        m_c = fmin(fmin(cur.bx, cur.bn), cur.pn);
         sP[q] = M_c;
         sPm[q] = m_c;
     } else if constexpr (!kPass) {
@@ -561,9 +569,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             zmx_c = fmax(fmax(fmax(pL, pR), fmax(pD, pU)), zlo ? cur.pn : fmax(cur.pn, pn_m1));
             zmn_c = fmin(fmin(fmin(pL, pR), fmin(pD, pU)), zlo ? cur.pn : fmin(cur.pn, pn_m1));
             if (MODE == kModeHead && NONOS && is_out && own_plane) {
-                // running bounds for the next pass: max/min(psi^n, psi1)
-                bstore<T>(plane_rsrc<T>(io.mx, t, pc_cells), b_c, fmax(cur.pn, p1_c));
-                bstore<T>(plane_rsrc<T>(io.mn, t, pc_cells), b_c, fmin(cur.pn, p1_c));
+                // psi1 for the next pass's bounds (psi^n stays in the input)
+                bstore<T>(plane_rsrc<T>(io.mx, t, pc_cells), b_c, p1_c);
             }
         }
         sQ[s0][q] = p1_c;  // psi1(t-3) of this slot was last read before (B)
@@ -829,7 +836,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         if constexpr (kPass && NONOS) {
             // running bounds of plane t+1 for the next iteration's stencil;
             // every read of sP/sPm of plane t happened before (D)
-            const T M_n = fmax(nx1.bx, nx1.pn), m_n = fmin(nx1.bn, nx1.pn);
+            const T M_n = fmax(fmax(nx1.bx, nx1.bn), nx1.pn);
+            const T m_n = fmin(fmin(nx1.bx, nx1.bn), nx1.pn);
             sP[q] = M_n;
             sPm[q] = m_n;
             M_m1 = M_c;

@@ -8,15 +8,17 @@
 // psi^n and every iterate of the step so far.  A step of iord = k + 1 is a
 // chain of k launches of the fused march (mpdata_march.h):
 //   head  psi^n -> psi^(2), the ordinary fused step, which also writes its
-//         limited velocity (face arrays) and the running bounds
-//         max/min(psi^n, psi1) cell by cell;
+//         limited velocity (face arrays) and psi1;
 //   mid   psi^(j) -> psi^(j+1), one further pass that reads the iterate and
-//         the running bounds in place of the donor-cell pass and writes its
+//         two bound arrays in place of the donor-cell pass and writes its
 //         velocity and the running bounds max/min(bounds, psi^(j)) on;
 //   last  the final pass, which writes psi^(n+1) only.
-// The running bounds are what makes one march per pass enough: the 7-point
-// max/min over several fields equals the 7-point max/min of their
-// cell-by-cell max/min.
+// The bounds of a pass are the cell-by-cell max(bx, bn, iterate) and
+// min(bx, bn, iterate) of two arrays and the iterate: psi1 and psi^n after
+// the head launch (psi^n is still the step's input), the running maximum and
+// minimum after a middle one.  They are what makes one march per pass
+// enough: the 7-point max/min over several fields equals the 7-point max/min
+// of their cell-by-cell max/min.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>

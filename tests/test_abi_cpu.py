@@ -100,17 +100,20 @@ def test_div_flag_needs_a_default_launch_shape():
 
 def test_more_corrective_passes_need_chain_buffers():
     """iord > 2: one more iterate, the three velocity face arrays and (with
-    the limiter) the two running-bound arrays; a second set from iord 4 on;
-    only on the default launch shape."""
+    the limiter) psi1 of the head launch; from iord 4 on a second set with
+    the running maximum and minimum of a middle pass, and from iord 5 on the
+    minimum of the first set too; only on the default launch shape."""
     n, nf = 32 * 32 * 16, 33 * 32 * 16 + 32 * 33 * 16 + 32 * 32 * 17
     b2 = _lib.mpdata_workspace_bytes(_params())
     b3 = _lib.mpdata_workspace_bytes(_params(iord=3))
     b4 = _lib.mpdata_workspace_bytes(_params(iord=4))
+    b5 = _lib.mpdata_workspace_bytes(_params(iord=5))
     b16 = _lib.mpdata_workspace_bytes(_params(iord=16))
-    assert b3 - b2 >= (3 * n + nf) * 8
+    assert (2 * n + nf) * 8 <= b3 - b2 < (3 * n + nf) * 8
     assert b4 - b3 >= (3 * n + nf) * 8
-    assert b16 > b4
-    assert _lib.mpdata_workspace_bytes(_params(iord=3, nonos=0)) <= b3 - 2 * n * 8
+    assert b5 - b4 >= n * 8
+    assert b16 > b5
+    assert _lib.mpdata_workspace_bytes(_params(iord=3, nonos=0)) <= b3 - n * 8
     assert _lib.mpdata_workspace_bytes(_params(iord=3, tile=5)) == b3
     assert _lib.mpdata_workspace_bytes(_params(iord=3, tile=1)) == 0
     assert _lib.mpdata_workspace_bytes(_params(iord=3, dtype=1, bc=1, tile=2)) > 0

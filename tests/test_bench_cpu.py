@@ -29,12 +29,12 @@ def test_algorithmic_bytes_are_five_reads_and_one_write():
 
 
 def test_chain_bytes_by_design():
-    """iord 3 = head (5 in, psi out, 3 velocity faces, 2 bound arrays) + last
-    (iterate, h, 2 bounds and 3 velocity faces in, psi out)."""
+    """iord 3 = head (5 in, psi out, 3 velocity faces, psi1) + last
+    (iterate, h, psi1, psi^n and 3 velocity faces in, psi out)."""
     nz, ny, nx = 4, 5, 6
     n = nx * ny * nz
     faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
-    head = (3 * n + faces) + faces + 2 * n
+    head = (3 * n + faces) + faces + n
     last = 4 * n + faces + n
     assert bench.chain_bytes((nz, ny, nx), 8, 3) == 8 * (head + last)
     mid = 4 * n + faces + 3 * n + faces
