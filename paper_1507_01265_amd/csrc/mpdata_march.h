@@ -413,10 +413,6 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     // the march advances it by one per iteration without a division
     auto plane_of = [&](int t) { return cell_of<OPZ>(t, nz); };
     auto zface_of = [&](int t) { return face_lo<OPZ>(t, nz); };
-    auto next_plane = [&](int k, int t_next) {
-        if (OPZ) return clampi(t_next, 0, nz - 1);
-        return k + 1 == nz ? 0 : k + 1;
-    };
     auto load_a = [&](int k, PlaneA<T> &r) {
         const Rsrc hp = plane_rsrc(g.h, k, pc_cells);
         const Rsrc u1p = plane_rsrc(g.u1, k, pc_u1);
@@ -507,13 +503,16 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     T fc3_m2 = T(0), fc3_m3 = T(0);             // corrective flux, faces t-2, t-3
     T fc1_m3 = T(0), fc2_m3 = T(0);             // corrective fluxes, lower x/y faces of plane t-3
 
-    auto iter = [&](const int t, auto slot) {
+    // zopen: the z-boundary handling of this iteration (OPZ, or false on the
+    // planes away from an open top and bottom, where it is the identity)
+    auto iter = [&](const int t, auto slot, auto zopen) {
+        constexpr bool OZ = decltype(zopen)::value;
         constexpr int s0 = decltype(slot)::value;           // slot of plane t (held t-3)
         constexpr int s1 = (s0 + 2) % 3, s2 = (s0 + 1) % 3; // planes t-1, t-2
         load_a(ka, nxA);
-        load_b(kb, OPZ ? zface_of(t + 2) : kb, nx2);
+        load_b(kb, OZ ? zface_of(t + 2) : kb, nx2);
         ka = kb;
-        kb = next_plane(kb, t + 3);
+        kb = OZ ? clampi(t + 3, 0, nz - 1) : (kb + 1 == nz ? 0 : kb + 1);
         __syncthreads();  // (B) psi^n(t), sums/h of t-1, corrective y-fluxes of t-3 are visible
         // own-column values of planes t-1 .. t-3
         const T p1_m1 = r_p1_m1, p1_m2 = r_p1_m2, p1_m3 = r_p1_m3;
@@ -546,7 +545,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             // the in-plane 5-point stencil of plane t and the plane below it
             rh_c = rcp_nr(curA.h);
             p1_c = cur.pn;
-            const bool zlo = OPZ && t <= 0;
+            const bool zlo = OZ && t <= 0;
             zmx_c = fmax(fmax(fmax(sP[q + cxm], sP[q + cxp]), fmax(sP[q + cym], sP[q + cyp])),
                          zlo ? M_c : fmax(M_c, M_m1));
             zmn_c = fmin(fmin(fmin(sPm[q + cxm], sPm[q + cxp]), fmin(sPm[q + cym], sPm[q + cyp])),
@@ -565,7 +564,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             rh_c = rcp_nr(curA.h);
             p1_c = cur.pn - (((f1hi - f1lo) + (f2hi - f2lo)) + (f3hi - f3_c)) * rh_c;
             // (at an open bottom the plane below t is t itself, already counted)
-            const bool zlo = OPZ && t <= 0;
+            const bool zlo = OZ && t <= 0;
             zmx_c = fmax(fmax(fmax(pL, pR), fmax(pD, pU)), zlo ? cur.pn : fmax(cur.pn, pn_m1));
             zmn_c = fmin(fmin(fmin(pL, pR), fmin(pD, pU)), zlo ? cur.pn : fmin(cur.pn, pn_m1));
             if (MODE == kModeHead && NONOS && is_out && own_plane) {
@@ -594,7 +593,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             T yxp, yxm, yh, yc3, yc1, ylo, yd;   // cell a of the lower y-face
         } e{};
         if constexpr (kEarlyS3) {
-            const bool clo = OPZ && t - 1 <= 0;
+            const bool clo = OZ && t - 1 <= 0;
             const T *Qc = sQ[s1];
             const T *Qlo = clo ? sQ[s1] : sQ[s2];
             e.qd = Qc[q + YM], e.qyp = Qc[q + cyp], e.qym = Qc[q + cym];
@@ -620,7 +619,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         {
             // ---- S3 at plane p = t-1 (lower x- and y-faces) and on face t
             const int p = t - 1;
-            const bool clo = OPZ && p <= 0, chi = OPZ && p >= nz - 1;
+            const bool clo = OZ && p <= 0, chi = OZ && p >= nz - 1;
             const T *Qc = sQ[s1];
             const T *Qb = sQ[s0];
             const T *Qlo = clo ? sQ[s1] : sQ[s2];
@@ -740,7 +739,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                                           c2_m1 + c2_c, av(Qb[q + cyp]) + av(qyp_),
                                           av(Qb[q + cym]) + av(qym_), eps, d_m1 + d_c);
             }
-            if (OPZ && (t <= 0 || t >= nz)) v3 = T(0);
+            if (OZ && (t <= 0 || t >= nz)) v3 = T(0);
             if (NONOS) {
                 // ---- S4 bounds at plane p
                 if constexpr (kPass) {
@@ -805,7 +804,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             }
             if (zero_v1) vt1 = T(0);
             if (zero_v2) vt2 = T(0);
-            if (OPZ && (t - 1 <= 0 || t - 1 >= nz)) vt3 = T(0);
+            if (OZ && (t - 1 <= 0 || t - 1 >= nz)) vt3 = T(0);
             if constexpr (kOuts) {
                 // the limited velocity of the segment's planes and of its
                 // z-faces (face nz from the segment that ends there)
@@ -884,21 +883,40 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     // Unrolled by three so the psi1 planes sit in fixed slots (slot of plane
     // t = (t - t0 + shift) mod 3); the iteration count modulo three is run
     // first, in the last slots, so that no iteration is wasted.
+    // With an open top and bottom, groups of three iterations on the planes
+    // t in [2, nz - 4] (no boundary face or clamped plane among the ones an
+    // iteration touches) take the code without the z-boundary handling.
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    using S2 = std::integral_constant<int, 2>;
+    using ZO = std::bool_constant<OPZ>;
     int t = t0;
     switch ((tend - t0 + 1) % 3) {
     case 2:
-        iter(t++, std::integral_constant<int, 1>{});
+        iter(t++, S1{}, ZO{});
         [[fallthrough]];
     case 1:
-        iter(t++, std::integral_constant<int, 2>{});
+        iter(t++, S2{}, ZO{});
         break;
     default:
         break;
     }
+    if constexpr (OPZ) {
+        for (; t <= tend && t < 2; t += 3) {
+            iter(t, S0{}, ZO{});
+            iter(t + 1, S1{}, ZO{});
+            iter(t + 2, S2{}, ZO{});
+        }
+        for (; t <= tend && t + 2 <= nz - 4; t += 3) {
+            iter(t, S0{}, std::false_type{});
+            iter(t + 1, S1{}, std::false_type{});
+            iter(t + 2, S2{}, std::false_type{});
+        }
+    }
     for (; t <= tend; t += 3) {
-        iter(t, std::integral_constant<int, 0>{});
-        iter(t + 1, std::integral_constant<int, 1>{});
-        iter(t + 2, std::integral_constant<int, 2>{});
+        iter(t, S0{}, ZO{});
+        iter(t + 1, S1{}, ZO{});
+        iter(t + 2, S2{}, ZO{});
     }
 }
 
