@@ -583,10 +583,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         // FP32, open in z, 32x32 regions: the LDS operands of S3 at plane t-1
         // that were complete at (B) -- psi1 of planes t-1 and t-2, h and the
         // Courant sums of plane t-1 -- are read in this phase, beside the S1
-        // arithmetic, so that only psi1 of plane t waits for (D) (2.8 % faster
-        // open FP32 step, measured; 1.8 % slower with 32x24 regions and 4 %
-        // slower on periodic grids).  FP64 has no registers to hold them
-        // across (D).
+        // arithmetic, so that only psi1 of plane t waits for (D) (2.2 % faster
+        // open FP32 step, measured, also in the iterations without the
+        // z-boundary handling; 1.8 % slower with 32x24 regions and 4 % slower
+        // on periodic grids).  FP64 has no registers to hold them across (D).
         struct {
             T qd, qyp, qym, qa, qxp, qxm;        // psi1(t-1), own stencil
             T xh, xc2, xc3, xqyp, xqym, xlo, xd; // cell a of the lower x-face
