@@ -398,3 +398,24 @@ def test_open_grid_interior_and_edge_tiles(orc, dtype):
             want = oracle_run(orc, g.as_f64(), n, **opts)
             got = gpu_run(g, n, dtype=torch.float32, **opts)
             assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_open_column_cut_into_shares(orc, dtype):
+    """One 20x20 tile with 200 planes: the plan cuts the column into
+    contiguous shares of about 25 planes, so most segments start (and prime
+    their pipeline) on planes away from the open top and bottom, where the
+    march runs without the z-boundary handling; options and more passes
+    too."""
+    f = inputs.random_smooth(40, (200, 20, 20), bc=1, cmax=0.15)
+    for n, opts in ((3, {}), (2, {"div": True}), (2, {"iord": 3})):
+        print(f"{dtype} {opts}", flush=True)
+        if dtype == "fp64":
+            want = oracle_run(orc, f, n, **opts)
+            assert rel_linf(gpu_run(f, n, **opts), want) <= 1e-12
+        else:
+            g = f.astype(np.float32)
+            want = oracle_run(orc, g.as_f64(), n, **opts)
+            got = gpu_run(g, n, dtype=torch.float32, **opts)
+            scale = opts.get("iord", 2) / 2
+            assert rel_linf(got, want) <= 2e-6 * n * scale and rel_l2(got, want) <= 5e-7 * n * scale
