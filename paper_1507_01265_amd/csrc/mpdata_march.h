@@ -883,9 +883,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     // Unrolled by three so the psi1 planes sit in fixed slots (slot of plane
     // t = (t - t0 + shift) mod 3); the iteration count modulo three is run
     // first, in the last slots, so that no iteration is wasted.
-    // With an open top and bottom, groups of three iterations on the planes
-    // t in [2, nz - 4] (no boundary face or clamped plane among the ones an
-    // iteration touches) take the code without the z-boundary handling.
+    // With an open top and bottom, groups of three iterations t in
+    // [2, nz - 4] take the code without the z-boundary handling: every
+    // z-boundary test of such an iteration is false, and the planes it loads
+    // (up to t + 3) need no clamping.
     using S0 = std::integral_constant<int, 0>;
     using S1 = std::integral_constant<int, 1>;
     using S2 = std::integral_constant<int, 2>;
