@@ -14,6 +14,10 @@ its memory returned to the budget.  Latency = result on the host - arrival.
 Results do not depend on the company a request keeps: every cell of a grid
 is computed by the same operations whatever the plan, so a request served
 alone and in a mix gives the same bits.
+
+A request that fails (refused at admission, a step that cannot be enqueued,
+a result that is not finite) is retired as failed with its reason; its slot
+and budget are released and the loop carries on with the others.
 """
 from __future__ import annotations
 
@@ -41,7 +45,8 @@ class Pool:
         shared = _lib.mpdata_params(1, 1, 1, DTYPES[dtype], BC[bc], 2, int(bool(nonos)), tile, 0,
                                     0, eps)
         ws = _lib.mpdata_pool_workspace_bytes(max_grids, max_segments)
-        self.workspace = torch.empty(ws, dtype=torch.uint8, device=device)
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(ws, dtype=torch.uint8, device=device)
         self._p = None
         self._p = _lib.mpdata_pool_create(shared, max_grids, max_segments,
                                           self.workspace.data_ptr(), ws, self.stream.cuda_stream)
@@ -86,6 +91,8 @@ def request_bytes(req: Request) -> int:
 
 @dataclasses.dataclass
 class Done:
+    """A retired request.  ``error`` is None for a request served to the
+    end; otherwise it says why the request failed (its result is None)."""
     rid: int
     arrival: float
     admitted: float
@@ -94,6 +101,7 @@ class Done:
     steps: int
     fp32: bool
     result: np.ndarray | None = None
+    error: str | None = None
 
 
 class Scheduler:
@@ -153,54 +161,142 @@ class Scheduler:
                 fin.append(req)
         return fin
 
+    def drop(self, rid):
+        """Takes a failed member out before its steps are done and releases
+        its budget (no-op for a rid that is not a member)."""
+        req = self.reqs.pop(rid, None)
+        if req is None:
+            return None
+        del self.left[rid]
+        self.used -= self.size_of(req)
+        return req
+
     @property
     def idle(self):
         return not self.left and not self.queue
 
 
-class Server:
-    """GPU executor of a :class:`Scheduler`: one pool per precision, fields
-    built on a side stream, results copied to the host at retirement."""
+class GpuExecutor:
+    """The device side of the server: one pool per precision on the compute
+    stream; a newcomer's fields are built on a side stream and validated
+    there when it joins its pool."""
 
-    def __init__(self, budget_bytes: float, *, k_max: int = 8, keep_results=False,
-                 device="cuda", nonos=True):
-        self.sched = Scheduler(budget_bytes, k_max)
-        self.keep = keep_results
+    def __init__(self, device="cuda", nonos=True):
         self.device = device
         self.compute = torch.cuda.current_stream()
         self.side = torch.cuda.Stream()
         self.pools = {True: Pool(torch.float32, nonos=nonos, stream=self.compute),
                       False: Pool(torch.float64, nonos=nonos, stream=self.compute)}
-        self.stats = collections.Counter()
+
+    def add(self, req):
+        """Resident fields of a request, joined to its pool (raises if the
+        library refuses them)."""
+        with torch.cuda.stream(self.side):
+            fields = rotation_request_device(req, self.device)
+            scratch = torch.empty_like(fields[0])
+        slot = self.pools[req.fp32].add(fields, scratch, validate_stream=self.side)
+        return dict(fields=fields, scratch=scratch, slot=slot, fp32=req.fp32)
+
+    def launch(self, k):
+        """Enqueues k steps of every non-empty pool; returns (event,
+        {fp32: error}) for the pools whose step could not be enqueued."""
+        failed = {}
+        for fp32, pool in self.pools.items():
+            if pool.size:
+                try:
+                    pool.step(k)
+                except _lib.MpdataError as e:
+                    failed[fp32] = f"step: {e}"
+        ev = torch.cuda.Event()
+        ev.record(self.compute)
+        return ev, failed
+
+    def wait(self, ev):
+        ev.synchronize()
+
+    def result(self, handle):
+        """The state of a member on the host."""
+        return handle["fields"][0].cpu().numpy()
+
+    def remove(self, handle):
+        self.pools[handle["fp32"]].remove(handle["slot"])
 
     def close(self):
         for p in self.pools.values():
             p.close()
 
+
+class Server:
+    """Continuous batching of a :class:`Scheduler` over an executor (by
+    default :class:`GpuExecutor`).
+
+    A request that fails -- its fields refused when it joins, its pool's
+    step not enqueued, or a result that is not finite or cannot be read back
+    at retirement -- is retired as failed (``Done.error``): its slot and its
+    budget are released and every other request carries on."""
+
+    def __init__(self, budget_bytes: float, *, k_max: int = 8, keep_results=False,
+                 device="cuda", nonos=True, executor=None):
+        self.sched = Scheduler(budget_bytes, k_max)
+        self.keep = keep_results
+        self.ex = executor if executor is not None else GpuExecutor(device, nonos)
+        self.stats = collections.Counter()
+
+    def close(self):
+        self.ex.close()
+
     def run(self, requests, *, realtime=True, log_every=0.0):
         """Serve ``requests``.  With ``realtime`` the arrivals are replayed
         against the wall clock; otherwise all requests are present at time 0
         (a saturation run).  Returns the list of :class:`Done` in completion
-        order."""
-        sched = self.sched
+        order (failed requests included)."""
+        sched, ex = self.sched, self.ex
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
-        members = {}           # rid -> dict(fields, scratch, slot, admitted)
+        members = {}           # rid -> dict(handle, admitted)
         done = []
         t0 = time.perf_counter()
         last_log = t0
         now = lambda: time.perf_counter() - t0
+
+        def fail(req, admitted, why):
+            self.stats["failed"] += 1
+            done.append(Done(req.rid, req.arrival, admitted, now(), req.cells, req.steps,
+                             req.fp32, None, why))
 
         def arrivals_and_admission():
             t = now() if realtime else float("inf")
             while pending and pending[0].arrival <= t:
                 sched.arrive(pending.popleft())
             for req in sched.admit():
-                with torch.cuda.stream(self.side):
-                    fields = rotation_request_device(req, self.device)
-                    scratch = torch.empty_like(fields[0])
-                slot = self.pools[req.fp32].add(fields, scratch, validate_stream=self.side)
-                members[req.rid] = dict(fields=fields, scratch=scratch, slot=slot,
-                                        admitted=now())
+                try:
+                    handle = ex.add(req)
+                except Exception as e:       # refused: the others carry on
+                    sched.drop(req.rid)
+                    fail(req, now(), f"add: {e}")
+                    continue
+                if members:
+                    self.stats["joined_busy"] += 1   # others are resident
+                members[req.rid] = dict(handle=handle, admitted=now())
+
+        def retire(req, why=None):
+            m = members.pop(req.rid)
+            out = None
+            if why is None:
+                try:
+                    out = ex.result(m["handle"])
+                    if not np.isfinite(out).all():
+                        why = "result holds NaN or Inf"
+                except Exception as e:
+                    why = f"result: {e}"
+            try:
+                ex.remove(m["handle"])
+            except Exception as e:
+                why = why or f"remove: {e}"
+            if why is not None:
+                fail(req, m["admitted"], why)
+            else:
+                done.append(Done(req.rid, req.arrival, m["admitted"], now(), req.cells,
+                                 req.steps, req.fp32, out if self.keep else None))
 
         while pending or not sched.idle:
             arrivals_and_admission()
@@ -209,21 +305,19 @@ class Server:
                 if pending and realtime:
                     time.sleep(max(0.0, pending[0].arrival - now()))
                 continue
-            for pool in self.pools.values():
-                if pool.size:
-                    pool.step(k)
-            ev = torch.cuda.Event()
-            ev.record(self.compute)
+            ev, failed = ex.launch(k)
             self.stats["ticks"] += 1
             self.stats["steps"] += k
+            if failed:
+                # members of a pool whose step was not enqueued leave as failed
+                for rid in [r for r in tick_members if sched.reqs[r].fp32 in failed]:
+                    req = sched.drop(rid)
+                    retire(req, failed[req.fp32])
+                tick_members = [r for r in tick_members if r in sched.left]
             arrivals_and_admission()          # newcomers join the next tick
-            ev.synchronize()
+            ex.wait(ev)
             for req in sched.advance(tick_members, k):
-                m = members.pop(req.rid)
-                out = m["fields"][0].cpu()    # the result, on the host
-                self.pools[req.fp32].remove(m["slot"])
-                done.append(Done(req.rid, req.arrival, m["admitted"], now(), req.cells,
-                                 req.steps, req.fp32, out.numpy() if self.keep else None))
+                retire(req)
             if log_every and time.perf_counter() - last_log > log_every:
                 last_log = time.perf_counter()
                 print(f"# serve t={now():.1f}s done={len(done)} members={len(members)} "
@@ -236,11 +330,15 @@ class Server:
 
 
 def summarize(done, elapsed=None):
-    lat = np.array([d.finished - d.arrival for d in done]) * 1e3
-    cells = sum(d.cells * d.steps for d in done)
+    """Latency percentiles and throughput of the requests served to the end
+    (failed ones are counted apart)."""
+    ok = [d for d in done if d.error is None]
+    lat = np.array([d.finished - d.arrival for d in ok]) * 1e3
+    cells = sum(d.cells * d.steps for d in ok)
     span = elapsed if elapsed is not None else (max(d.finished for d in done) -
                                                 min(d.arrival for d in done))
-    return {"requests": len(done), "p50_ms": float(np.percentile(lat, 50)),
+    return {"requests": len(ok), "failed": len(done) - len(ok),
+            "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
             "max_ms": float(lat.max()), "cell_updates": cells, "seconds": span,
             "cell_updates_per_s": cells / span}
