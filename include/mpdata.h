@@ -30,8 +30,14 @@
  *    same value (checked by mpdata_create).
  *  - Element type: double for MPDATA_FP64; float for MPDATA_FP32, which
  *    stores fields and runs the bulk stencil in FP32 while the limiter's
- *    inflow/outflow sums, its divides and its min() run in FP64 and mass
- *    sums are compensated (double-double).
+ *    inflow/outflow sums and its divides run in FP64; each factor, capped
+ *    at 1, is rounded once to FP32 and the minimum of two factors is taken
+ *    on the rounded values, which equals the rounded FP64 minimum bit for
+ *    bit (rounding is monotone).  Mass sums are compensated (double-double).
+ *  - Range of psi: FP64 steps stay finite for |psi| below about 1e100 (the
+ *    pseudo-velocity divides once per face by a product of three ratio
+ *    denominators); FP32 steps scale that product exactly by powers of two
+ *    and stay finite for |psi| below about 1e37, at any small magnitude.
  *  - Pointers named "device" are device memory of the current HIP device;
  *    the caller owns them and keeps them alive until mpdata_destroy().  The
  *    library allocates no device memory: everything it needs beyond the
@@ -94,9 +100,13 @@ typedef struct {
                              from mpdata_tile_count()/mpdata_tile_info() */
     int32_t flags;        /* MPDATA_FLAG_* bits, 0 = defaults */
     int32_t reserved;     /* must be 0 */
-    double eps;           /* > 0, regularises the ratio denominators of the
+    double eps;           /* >= 1e-30 and finite (MPDATA_EINVAL otherwise),
+                             regularises the ratio denominators of the
                              pseudo-velocity and of the limiter; 1e-15 is the
-                             usual value */
+                             usual value.  The floor keeps the common
+                             denominators the kernels divide by (about
+                             h eps^3 in FP64 on a zero background, and
+                             (IN + eps)(OUT + eps) in the limiter) normal */
 } mpdata_params;
 
 typedef struct mpdata_ctx mpdata_ctx; /* opaque */
@@ -115,7 +125,7 @@ size_t mpdata_workspace_bytes(const mpdata_params *p);
  *   u1,u2,u3,h device, read-only for the lifetime of the context
  *   workspace  device, >= mpdata_workspace_bytes(p) bytes, 256-byte aligned
  *   stream     hipStream_t of the caller (NULL = default stream)
- * Checks: dims >= 1, enum ranges, eps > 0, non-NULL 16-byte-aligned
+ * Checks: dims >= 1, enum ranges, eps >= 1e-30, non-NULL 16-byte-aligned
  * pointers, h > 0 everywhere, and (periodic) face n == face 0 bit for bit
  * on every axis.  These checks read the arrays and synchronise the stream.
  * On success *out receives the context; on failure *out is set to NULL. */
@@ -149,7 +159,9 @@ int mpdata_sync(mpdata_ctx *ctx);
 /* Number of time steps executed since creation (or the last set_psi). */
 int64_t mpdata_steps_done(const mpdata_ctx *ctx);
 
-/* Releases the context (NULL-safe).  Never frees caller memory. */
+/* Waits for the work enqueued by the context, then releases it (NULL-safe);
+ * afterwards the caller may free the workspace and the arrays.  Never frees
+ * caller memory. */
 void mpdata_destroy(mpdata_ctx *ctx);
 
 /* Message of the last failed call on ctx ("" if none); with ctx == NULL the
@@ -263,7 +275,8 @@ int32_t mpdata_pool_size(const mpdata_pool *pool);             /* current member
 int mpdata_pool_sync(mpdata_pool *pool);
 void mpdata_pool_destroy(mpdata_pool *pool);                   /* NULL-safe */
 const char *mpdata_pool_last_error(const mpdata_pool *pool);   /* NULL: last create */
-void mpdata_batch_destroy(mpdata_batch *b);                 /* NULL-safe */
+void mpdata_batch_destroy(mpdata_batch *b);                 /* NULL-safe; waits for
+                                                               the batch's work first */
 const char *mpdata_batch_last_error(const mpdata_batch *b); /* NULL: last create */
 
 /* -------------------------------------- model-based load imbalancing (host)

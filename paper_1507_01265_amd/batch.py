@@ -57,7 +57,8 @@ class Batch:
         ws_bytes = _lib.mpdata_batch_workspace_bytes(self.params, max_seg, max_wg)
         if ws_bytes == 0:
             raise ValueError("invalid batch parameters")
-        self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=grids[0][0].device)
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=grids[0][0].device)
         self._b = None
         self._b = _lib.mpdata_batch_create(
             self.params, [g[0].data_ptr() for g in grids], [g[1].data_ptr() for g in grids],

@@ -75,7 +75,10 @@ const char *check_params(const mpdata_params *p)
     if (p->iord < 1 || p->iord > kMaxIord) return "iord must be 1 .. 16";
     if (p->nonos != 0 && p->nonos != 1) return "nonos must be 0 or 1";
     if (p->nonos && p->iord < 2) return "nonos needs iord >= 2";
-    if (!(p->eps > 0.0) || !isfinite(p->eps)) return "eps must be finite and > 0";
+    // the common denominator of the FP64 pseudo-velocity is about
+    // h eps^3 on a zero background and the limiter's (IN + eps)(OUT + eps)
+    // about eps^2: eps >= 1e-30 keeps both normal
+    if (!(p->eps >= 1e-30) || !isfinite(p->eps)) return "eps must be finite and >= 1e-30";
     if (p->flags & ~(MPDATA_FLAG_NO_GRAPH | MPDATA_FLAG_VSIGN | MPDATA_FLAG_DIV))
         return "unknown flag bits";
     if (p->reserved != 0) return "reserved must be 0";
@@ -1057,6 +1060,9 @@ int64_t mpdata_steps_done(const mpdata_ctx *c) { return c ? c->steps : -1; }
 void mpdata_destroy(mpdata_ctx *c)
 {
     if (!c) return;
+    // the caller may free the workspace once this returns: wait for the
+    // work still queued on it
+    (void)hipStreamSynchronize(c->e.stream);
     engine_release(c->e);
     delete c;
 }
@@ -1160,6 +1166,7 @@ int mpdata_batch_sync(mpdata_batch *b)
 void mpdata_batch_destroy(mpdata_batch *b)
 {
     if (!b) return;
+    (void)hipStreamSynchronize(b->e.stream);
     engine_release(b->e);
     delete b;
 }

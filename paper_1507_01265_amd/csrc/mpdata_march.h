@@ -137,14 +137,27 @@ template <> struct Tiny<float> { static constexpr float v = 1.17549435e-38f; };
 // is evaluated over one common denominator, so a face costs one division:
 //   V = [(|U| hs - 2U^2) nA dBs dBt - (U dA/4)(us nBs dBt + ut nBt dBs)]
 //       / (hs dA dBs dBt).
+// The quotient is homogeneous of degree zero in each of the pairs (nA, dA),
+// (nBs, dBs) and (nBt, dBt) on its own: scaling one pair by any factor
+// leaves V unchanged.
 // FP64 divides as written: for psi1 >= 0 (or the variable-sign option) every
 // ratio denominator is at least eps, so the common one is at least
-// hs eps^3 (about 1e-45), far inside the normal range; only a field of both
-// signs without the variable-sign option can zero it, and then V is Inf or
-// NaN exactly where the separate ratios divide by zero.  In FP32 eps^3
-// underflows: a common denominator below the smallest normal number in
-// magnitude (all neighbouring psi1 within eps of zero) gives V = 0.  A
-// negative denominator (a field below zero) divides like any other.
+// hs eps^3 (above 2e-90 for the smallest accepted eps, 1e-30), inside the
+// normal range, and below 1.8e308 while |psi1| stays below about 1e100.
+// FP32 would leave its range at both ends (the cubic product overflows for
+// |psi1| near 2e12 and underflows below about 5e-14, or wherever the
+// transverse sums vanish beside a small psi1), so each transverse pair is
+// first scaled by the power of two that brings its denominator to
+// [0.5, 1): an exact operation, so every field whose products stayed in
+// range keeps the same bits, and the common denominator becomes
+// hs dA [0.25, 1) -- at least hs eps / 4 and finite for any psi1 below
+// about 1e37.  The guard that remains (V = 0 for a denominator below the
+// smallest normal float) cannot fire on such a field unless hs eps / 4 is
+// below that number (a density below about 2e-23 at eps = 1e-15).
+// Only a field of both signs without the variable-sign option can zero a
+// ratio denominator: FP64 then gives Inf or NaN exactly where the separate
+// ratios divide by zero, FP32 gives V = 0 (the guard).  A negative
+// denominator (a field below zero) divides like any other.
 // With DIV the divergent-flow term -(1/4)(U/G) dv joins the numerator as
 // -(U/2) dv dA dBs dBt (dv: the centred divergence of the velocity field
 // across the face, the sum of the divergences of cells a and b).
@@ -153,8 +166,17 @@ __device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi
                                              T t_hi, T t_lo, T eps, T dv = T(0))
 {
     const T nA = pb - pa, dA = (pb + pa) + eps;
-    const T nBs = s_hi - s_lo, dBs = (s_hi + s_lo) + eps;
-    const T nBt = t_hi - t_lo, dBt = (t_hi + t_lo) + eps;
+    T nBs = s_hi - s_lo, dBs = (s_hi + s_lo) + eps;
+    T nBt = t_hi - t_lo, dBt = (t_hi + t_lo) + eps;
+    if constexpr (sizeof(T) == 4) {
+        // exact power-of-two scaling of each transverse pair (v_frexp_mant
+        // keeps the sign and returns 0 for 0)
+        const int es = __builtin_amdgcn_frexp_expf(dBs), et = __builtin_amdgcn_frexp_expf(dBt);
+        dBs = __builtin_amdgcn_frexp_mantf(dBs);
+        dBt = __builtin_amdgcn_frexp_mantf(dBt);
+        nBs = __builtin_amdgcn_ldexpf(nBs, -es);
+        nBt = __builtin_amdgcn_ldexpf(nBt, -et);
+    }
     const T P = dBs * dBt;
     const T c = fabs(U) * hs - T(2) * (U * U);
     const T cross = (us * nBs) * dBt + (ut * nBt) * dBs;
@@ -164,9 +186,6 @@ __device__ __forceinline__ T pseudo_velocity(T U, T hs, T pa, T pb, T us, T s_hi
     if constexpr (sizeof(T) == 8) {
         return div_nr(num, den);
     } else {
-        // FP32: the guard fires wherever psi1 vanishes around the face (eps^3
-        // underflows), and waves lying wholly in such a region skip the
-        // division
         return fabs(den) >= Tiny<T>::v ? div_nr(num, den) : T(0);
     }
 }

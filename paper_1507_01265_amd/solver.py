@@ -66,7 +66,10 @@ class Solver:
         if ws_bytes == 0:
             raise ValueError("invalid parameters: " + str(dict(nx=nx, ny=ny, nz=nz, bc=bc,
                                                                iord=iord, nonos=nonos)))
-        self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=psi.device)
+        # allocated on the stream the steps run on, so the caching allocator
+        # does not hand it out while they are queued
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=psi.device)
         self.psi, self.u1, self.u2, self.u3, self.h = psi, u1, u2, u3, h
         self._ctx = None
         self._ctx = _lib.mpdata_create(self.params, psi.data_ptr(), u1.data_ptr(), u2.data_ptr(),

@@ -66,7 +66,8 @@ def test_workspace_bytes():
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(nz=-1), dict(dtype=2), dict(bc=5),
                                  dict(iord=0), dict(iord=17), dict(iord=1, nonos=1), dict(nonos=2),
-                                 dict(eps=0.0), dict(eps=float("nan")), dict(tile=99),
+                                 dict(eps=0.0), dict(eps=float("nan")), dict(eps=9.9e-31),
+                                 dict(eps=1e-100), dict(eps=float("inf")), dict(tile=99),
                                  dict(nx=4096, ny=4096, nz=256),
                                  dict(nx=30000, ny=30000, nz=1)])
 def test_invalid_params_are_rejected(bad):
@@ -76,6 +77,16 @@ def test_invalid_params_are_rejected(bad):
         _lib.mpdata_create(p, 256, 256, 256, 256, 256, 256, 1 << 30, None)
     assert e.value.code == _lib.MPDATA_EINVAL
     assert _lib.mpdata_last_error(None)
+
+
+def test_eps_floor_keeps_the_common_denominators_normal():
+    """eps >= 1e-30: the FP64 pseudo-velocity divides by about h eps^3 on a
+    zero background, which stays a normal double (2e-90) at the floor."""
+    assert _lib.mpdata_workspace_bytes(_params(eps=1e-30)) > 0
+    assert _lib.mpdata_workspace_bytes(_params(eps=0.5)) > 0
+    assert _lib.mpdata_workspace_bytes(_params(eps=1e-31)) == 0
+    with pytest.raises(_lib.MpdataError, match="eps"):
+        _lib.mpdata_create(_params(eps=1e-40), 256, 256, 256, 256, 256, 256, 1 << 30, None)
 
 
 def test_vsign_flag_needs_a_default_launch_shape():

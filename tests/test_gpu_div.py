@@ -1,13 +1,15 @@
 """The divergent-flow term (MPDATA_FLAG_DIV) on the GPU against the oracle.
 
 random_smooth draws independent face Courant numbers, so its flows are
-divergent and the term is active.  FP64 bar: rel-Linf <= 1e-12; FP32 bar as
-for the plain step (2e-6 rel-Linf, 5e-7 rel-L2 per step).
+divergent and the term is active.  Bars as for the plain step
+(tests/bars.py): FP64 rel-Linf <= 1e-12; FP32 rel-Linf <= 1e-5 and rel-L2
+<= 2e-6.
 """
 import dataclasses
 
 import numpy as np
 import pytest
+from bars import check_fp32
 
 from paper_1507_01265_amd import inputs
 
@@ -65,7 +67,7 @@ def test_parity_fp32(orc, bc):
     n = 4
     want = oracle_run(orc, f.as_f64(), n, div=True)
     got = gpu_run(f, n, dtype=torch.float32, div=True)
-    assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
+    check_fp32(got, want, f"div bc {bc}")
 
 
 @pytest.mark.parametrize("bc", [0, 1], ids=["periodic", "open"])

@@ -1,15 +1,15 @@
 """More than one corrective pass (iord > 2) on the GPU against the oracle.
 
 The step is a chain of launches (the fused step, then one launch per further
-pass); these tests run it through the C ABI.  FP64 bar: rel-Linf <= 1e-12.
-FP32 bar: the FP32 path rounds about as often per corrective pass as per
-donor-cell pass, so the per-step allowance of iord 2 (2e-6 rel-Linf, 5e-7
-rel-L2 per step) is scaled by iord / 2.
+pass); these tests run it through the C ABI.  Bars as for one corrective
+pass (tests/bars.py): FP64 rel-Linf <= 1e-12; FP32 rel-Linf <= 1e-5 and
+rel-L2 <= 2e-6.
 """
 import dataclasses
 
 import numpy as np
 import pytest
+from bars import check_fp32
 
 from paper_1507_01265_amd import inputs
 
@@ -70,9 +70,7 @@ def test_parity_fp32(orc, bc):
     n, iord = 4, 3
     want = oracle_run(orc, f.as_f64(), n, iord=iord)
     got = gpu_run(f, n, dtype=torch.float32, iord=iord)
-    scale = iord / 2
-    assert rel_linf(got, want) <= 2e-6 * n * scale
-    assert rel_l2(got, want) <= 5e-7 * n * scale
+    check_fp32(got, want, f"iord {iord} bc {bc}")
 
 
 @pytest.mark.parametrize("nonos", [True, False], ids=["nonos", "unlimited"])

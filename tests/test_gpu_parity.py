@@ -1,13 +1,12 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
-FP64 bar: relative max-norm error <= 1e-12 (max|gpu - oracle| / max|oracle|).
-FP32 bar (FP32 storage and bulk arithmetic, FP64 limiter): the FP64 oracle
-runs on the same FP32-rounded inputs; per step the FP32 path commits a few
-units of FP32 rounding (2^-24 ~ 6e-8) per stage, so after n steps we allow
-rel-Linf <= 2e-6 * n and rel-L2 <= 5e-7 * n.
+The bars (FP64 rel-Linf <= 1e-12; FP32 rel-Linf <= 1e-5 and rel-L2 <= 2e-6
+against the FP64 oracle on the same FP32-rounded inputs, for runs of at most
+100 steps) are stated and derived in tests/bars.py.
 """
 import numpy as np
 import pytest
+from bars import FP32_DRIFT, check_fp32, check_fp64
 
 from paper_1507_01265_amd import inputs
 
@@ -220,9 +219,7 @@ def test_fp32_against_fp64_oracle(orc, bc):
     f = inputs.random_smooth(127, (12, 50, 70), bc=bc, cmax=0.15).astype(np.float32)
     want = oracle_run(orc, f.as_f64(), steps)
     got = gpu_run(f, steps, dtype=torch.float32)
-    e_inf, e_2 = rel_linf(got, want), rel_l2(got, want)
-    print(f"fp32 bc={bc} rel-Linf {e_inf:.3e} rel-L2 {e_2:.3e}")
-    assert e_inf <= 2e-6 * steps and e_2 <= 5e-7 * steps
+    check_fp32(got, want, f"bc={bc}")
 
 
 def test_fp32_every_tile_agrees(orc):
@@ -263,7 +260,7 @@ def test_vsign_parity_fp32(orc, bc):
     n = 4
     want = oracle_run(orc, f.as_f64(), n, vsign=True)
     got = gpu_run(f, n, dtype=torch.float32, vsign=True)
-    assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
+    check_fp32(got, want)
 
 
 def test_vsign_is_the_default_scheme_on_positive_fields():
@@ -311,16 +308,91 @@ def test_full_size_rotation_fp64_100_steps(orc):
 @pytest.mark.slow
 def test_full_size_rotation_fp32_100_steps(orc):
     """512x256x64 rotation in FP32 + FP64 limiter, the benchmark's 100 steps,
-    against the FP64 oracle within the per-step FP32 allowance; the zero
-    background stays non-negative."""
+    against the FP64 oracle within the FP32 bar; the zero background stays
+    non-negative and the mass drift stays within the FP32 bar."""
     f = inputs.rotation().astype(np.float32)
     n = 100
     want = oracle_run(orc, f.as_f64(), n)
-    got = gpu_run(f, n, dtype=torch.float32)
-    print(f"rel-Linf {rel_linf(got, want):.3e} rel-L2 {rel_l2(got, want):.3e} min {got.min():.3e}",
-          flush=True)
-    assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
+    s = _solver(f, dtype=torch.float32)
+    m0 = s.mass()
+    s.step(n)
+    m1 = s.mass()
+    got = s.psi.cpu().numpy().astype(np.float64)
+    s.close()
+    drift = (m1 - m0) / m0
+    check_fp32(got, want, f"rotation 100 steps min {got.min():.3e} drift {drift:.3e}")
     assert got.min() >= 0.0
+    assert abs(drift) <= FP32_DRIFT
+
+
+@pytest.mark.slow
+def test_full_size_streamfunction_fp32_50_steps(orc):
+    """1024x512x64 open domain, FP32 + FP64 limiter, the configured 50 steps,
+    against the FP64 oracle; the open-boundary mass budget holds on the GPU
+    side: the change of the mass over the run equals the net donor-cell
+    inflow through the six boundary faces summed over the steps (the
+    corrective fluxes there are zero)."""
+    f = inputs.streamfunction().astype(np.float32)
+    n = 50
+    want = oracle_run(orc, f.as_f64(), n)
+    s = _solver(f, dtype=torch.float32, graph=False)
+    u = [t.astype(np.float64) for t in (f.u1, f.u2, f.u3)]
+    m0 = s.mass()
+    inflow = 0.0
+    for _ in range(n):
+        psi_n = s.psi.cpu().numpy().astype(np.float64)
+        inflow += orc.open_inflow(psi_n, *u)
+        s.step(1)
+    m1 = s.mass()
+    got = s.psi.cpu().numpy().astype(np.float64)
+    s.close()
+    check_fp32(got, want, "streamfunction 50 steps")
+    budget = abs((m1 - m0) - inflow) / abs(m0)
+    print(f"mass change {(m1 - m0) / m0:.3e}, budget residual {budget:.3e}", flush=True)
+    assert budget <= 1e-7
+
+
+@pytest.mark.parametrize("e2", [41, -44], ids=["x2^41", "x2^-44"])
+@pytest.mark.parametrize("vsign", [False, True], ids=["plain", "vsign"])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_scaled_field_parity(orc, dtype, vsign, e2):
+    """A field scaled by 2^41 (about 2e12) or 2^-44 (about 6e-14): the
+    pseudo-velocity's single division over a product of three ratio
+    denominators must stay in range (in FP32 each transverse pair is scaled
+    by a power of two first).  Positive field, and a sign-changing one with
+    the variable-sign option; the oracle runs on the same rounded inputs."""
+    import dataclasses
+    shape = (13, 45, 70)
+    f = _mixed_sign(41, shape) if vsign else inputs.random_smooth(41, shape, cmax=0.15)
+    f = dataclasses.replace(f, psi=f.psi * 2.0 ** e2)
+    n = 4
+    if dtype == "fp64":
+        check_fp64(gpu_run(f, n, vsign=vsign), oracle_run(orc, f, n, vsign=vsign), f"2^{e2}")
+    else:
+        g = f.astype(np.float32)
+        want = oracle_run(orc, g.as_f64(), n, vsign=vsign)
+        check_fp32(gpu_run(g, n, dtype=torch.float32, vsign=vsign), want, f"2^{e2}")
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_thin_row_of_small_values_on_zero_background(orc, dtype):
+    """psi = 0 except one x-row of values near 1e-9: on the row's x-faces
+    the transverse ratio sums hold eps alone, so the product of the three
+    ratio denominators is about h psi eps^2 (below the smallest normal
+    float); the pseudo-velocity must still match the oracle's separate
+    ratios."""
+    import dataclasses
+    f = inputs.random_smooth(42, (9, 21, 64), cmax=0.15)
+    psi = np.zeros_like(f.psi)
+    x = np.arange(64)
+    psi[4, 10, :] = 1e-9 * (1.5 + np.sin(2 * np.pi * x / 64))
+    f = dataclasses.replace(f, psi=psi)
+    n = 3
+    if dtype == "fp64":
+        check_fp64(gpu_run(f, n), oracle_run(orc, f, n), "thin row")
+    else:
+        g = f.astype(np.float32)
+        check_fp32(gpu_run(g, n, dtype=torch.float32), oracle_run(orc, g.as_f64(), n), "thin row")
 
 
 @pytest.mark.slow
@@ -338,7 +410,7 @@ def test_full_size_streamfunction_fp32(orc):
     f = inputs.streamfunction().astype(np.float32)
     want = oracle_run(orc, f.as_f64(), 1)
     got = gpu_run(f, 1, dtype=torch.float32)
-    assert rel_linf(got, want) <= 2e-6 and rel_l2(got, want) <= 5e-7
+    check_fp32(got, want, "streamfunction 1 step")
 
 
 @pytest.mark.parametrize("bc", [0, 1])
@@ -363,7 +435,7 @@ def test_negative_field_parity_fp32(orc):
     n = 4
     want = oracle_run(orc, f.as_f64(), n, nonos=False)
     got = gpu_run(f, n, dtype=torch.float32, nonos=False)
-    assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
+    check_fp32(got, want)
 
 
 def _interior_tiles(shape, rx, ry):
@@ -397,7 +469,7 @@ def test_open_grid_interior_and_edge_tiles(orc, dtype):
             g = g.astype(np.float32)
             want = oracle_run(orc, g.as_f64(), n, **opts)
             got = gpu_run(g, n, dtype=torch.float32, **opts)
-            assert rel_linf(got, want) <= 2e-6 * n and rel_l2(got, want) <= 5e-7 * n
+            check_fp32(got, want)
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
@@ -417,5 +489,4 @@ def test_open_column_cut_into_shares(orc, dtype):
             g = f.astype(np.float32)
             want = oracle_run(orc, g.as_f64(), n, **opts)
             got = gpu_run(g, n, dtype=torch.float32, **opts)
-            scale = opts.get("iord", 2) / 2
-            assert rel_linf(got, want) <= 2e-6 * n * scale and rel_l2(got, want) <= 5e-7 * n * scale
+            check_fp32(got, want, str(opts))
