@@ -8,10 +8,15 @@ grid in FP64 (cone + slotted cube on a zero background, h in [0.8, 1.2]);
 inputs are synthetic, seeded and resident in HBM before the timed region.
 
 Prints ONE JSON line: cell-updates/s over exactly --steps timed steps after
---warmup untimed ones, the HBM roofline of the fused kernel (algorithmic
-bytes per launch / average launch time from HIP events on the solver's
-stream), and the FP64 CPU oracle timed on a bounded sample of the same
-workload on the host's cores.
+--warmup untimed ones; the rooflines of the fused kernel at the launch time
+measured with HIP events on the solver's stream -- HBM (algorithmic bytes per
+launch against 8 TB/s) and VALU issue (busy SIMD-cycles per launch from the
+committed counters of the same kernel source, against 1024 SIMDs x 2.4 GHz),
+`roofline.bound` naming the one closer to saturation; the errors of a fresh
+run of E steps against the FP64 oracle's E steps on the same inputs
+(rel-Linf, rel-L2, mass drift); and that oracle run, timed on the host's
+cores, as the CPU baseline.  The default workload adds an `fp32` object: the
+same grid in FP32 + FP64 limiter, timed and checked the same way.
 """
 from __future__ import annotations
 
@@ -92,31 +97,84 @@ def chain_bytes(shape, word, iord, nonos=True):
 
 PROFILES = {"rotation-fp64": "step_kernel_rotation_512x256x64_fp64.md",
             "rotation-fp32": "step_kernel_rotation_512x256x64_fp32.md",
-            "streamfunction-fp32": "step_kernel_streamfunction_1024x512x64_fp32.md"}
+            "streamfunction-fp32": "step_kernel_streamfunction_1024x512x64_fp32.md",
+            "streamfunction-fp64": "step_kernel_streamfunction_1024x512x64_fp64.md"}
+
+# VALU issue peak: 256 CUs x 4 SIMDs, one issue cycle per SIMD per clock
+SIMDS = 256 * 4
+CLOCK_GHZ = 2.4
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    summary of this workload (FETCH_SIZE and WRITE_SIZE runs, each scaled by
-    the same counter on a 512 MiB copy), or None when there is none or the
-    kernel source changed since the counters were taken."""
+def kernel_source_sha():
+    """sha256 of the step kernel's source: the march and the kernel file,
+    concatenated."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_1507_01265_amd", "csrc")
+    return hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                   for f in ("mpdata_march.h", "mpdata_step.hip"))).hexdigest()
+
+
+def profile_figures(workload):
+    """Per-launch figures of the step kernel from the committed rocprofv3
+    summary of this workload (lines "key: value"), or {} when there is none
+    or the kernel source changed since the counters were taken:
+    traffic_bytes_per_launch (FETCH_SIZE and WRITE_SIZE runs, each scaled by
+    the same counter on a 512 MiB copy), valu_insts_per_launch
+    (SQ_INSTS_VALU, wave instructions) and valu_quad_cycles_per_launch
+    (SQ_ACTIVE_INST_VALU, quad-cycles a SIMD's VALU is busy, summed)."""
     name = PROFILES.get(workload)
     path = os.path.join(ROOT, "profiles", name) if name else None
     if not path or not os.path.exists(path):
-        return None
+        return {}
     fields = {}
     for line in open(path):
-        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+        if ":" in line:
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    # the step kernel's source: the march and the kernel file, concatenated
-    csrc = os.path.join(ROOT, "paper_1507_01265_amd", "csrc")
-    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                  for f in ("mpdata_march.h", "mpdata_step.hip"))).hexdigest()
-    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    if fields.get("kernel_source_sha256") != kernel_source_sha():
+        return {}
+    out = {}
+    for k in ("traffic_bytes_per_launch", "valu_insts_per_launch", "valu_quad_cycles_per_launch"):
+        if k in fields:
+            out[k] = float(fields[k])
+    return out
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed profile, or None."""
+    return profile_figures(workload).get("traffic_bytes_per_launch")
+
+
+def roofline(workload, shape, word, ms_per_step):
+    """Roofline objects of the step kernel at the measured launch time.
+
+    HBM: algorithmic bytes per launch (5 reads + 1 write per cell) over the
+    launch time against the 8 TB/s peak.  VALU: the SIMDs' VALU busy cycles
+    per launch (SQ_ACTIVE_INST_VALU x 4, from the committed counters of the
+    same kernel source) over the launch time against 1024 SIMDs x 2.4 GHz;
+    lane instructions per output cell-step from SQ_INSTS_VALU x 64.
+    `bound` names the roof closer to saturation; both are reported."""
+    abytes = algorithmic_bytes(shape, word)
+    t = ms_per_step / 1e3
+    achieved = abytes / t / 1e9
+    prof = profile_figures(workload)
+    hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": prof.get("traffic_bytes_per_launch"),
+           "algorithmic_bytes_per_launch": abytes}
+    if "valu_quad_cycles_per_launch" not in prof:
+        return hbm, None
+    nz, ny, nx = shape
+    cyc = 4.0 * prof["valu_quad_cycles_per_launch"]
+    valu = {"achieved": cyc / t / 1e12, "peak": SIMDS * CLOCK_GHZ / 1e3,
+            "unit": "T VALU-busy SIMD-cycles/s", "frac": cyc / t / (SIMDS * CLOCK_GHZ * 1e9),
+            "lane_insts_per_cell_step": prof.get("valu_insts_per_launch", 0.0) * 64 / (nx * ny * nz)}
+    if valu["frac"] > hbm["frac"]:
+        main = {"bound": "alu", "achieved": valu["achieved"], "peak": valu["peak"],
+                "unit": valu["unit"], "frac": valu["frac"], "traffic": hbm["traffic"],
+                "hbm": {k: hbm[k] for k in ("achieved", "peak", "unit", "frac",
+                                            "algorithmic_bytes_per_launch")}}
+        return main, valu
+    return hbm, valu
 
 
 def make_fields(kind):
@@ -197,21 +255,44 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(fields, budget_s=12.0, max_steps=40, iord=2, div=False):
-    """The FP64 oracle as it stands, stepped on the host until the budget is
-    spent (at least 2 steps)."""
+def error_run(fields, dtype_tag, steps, iord=2, div=False):
+    """A fresh run of `steps` steps on the GPU from the workload's initial
+    state: psi after the run (as float64) and the relative mass drift."""
+    import numpy as np
+    import torch
+    from paper_1507_01265_amd.solver import Solver
+    tdt = torch.float64 if dtype_tag == "f64" else torch.float32
+    f = fields if dtype_tag == "f64" else fields.astype(np.float32)
+    s = Solver.from_numpy(f, dtype=tdt, device="cuda", iord=iord, div=div)
+    m0 = s.mass()
+    s.step(steps)
+    m1 = s.mass()
+    out = s.psi.cpu().numpy().astype(np.float64)
+    s.close()
+    return out, (m1 - m0) / m0
+
+
+def oracle_steps(fields, steps, iord=2, div=False):
+    """The FP64 oracle stepped `steps` times on the host (its inputs: the
+    workload's FP64 fields, or their FP32 roundings for an FP32 result);
+    returns psi and the seconds it took."""
     import oracle
     f = fields
-    psi = f.psi
-    steps = 0
     t0 = time.perf_counter()
-    while True:
-        psi = oracle.step(psi, f.u1, f.u2, f.u3, f.h, bc=f.bc, iord=iord, div=div)
-        steps += 1
-        el = time.perf_counter() - t0
-        if (steps >= 2 and el >= budget_s) or steps >= max_steps:
-            break
-    return steps, el
+    psi = oracle.run(f.psi, f.u1, f.u2, f.u3, f.h, steps, bc=f.bc, iord=iord, div=div)
+    return psi, time.perf_counter() - t0
+
+
+def errors(got, want, drift, steps):
+    """Relative errors of a GPU result against the oracle on the same
+    inputs: max-norm and 2-norm over the field's own norm, and the GPU
+    run's relative mass drift (on an open grid that is the net boundary
+    flux, not an error)."""
+    import numpy as np
+    d = got - want
+    return {"rel_linf": float(np.abs(d).max() / np.abs(want).max()),
+            "rel_l2": float(np.linalg.norm(d.ravel()) / np.linalg.norm(want.ravel())),
+            "mass_drift": float(drift), "steps": int(steps), "against": "FP64 oracle, same inputs"}
 
 
 def time_region(fn, stream):
@@ -351,6 +432,70 @@ def bench_teams(args):
             "teams": ex}
 
 
+# steps of the workload's configured run (the error check runs at most
+# this many)
+RUN_STEPS = {"rotation": 100, "divergent": 100, "streamfunction": 50}
+
+
+def error_steps(args, kind):
+    return args.error_steps or min(args.steps, RUN_STEPS.get(kind, args.steps))
+
+
+def single_grid(args, workload, fields, sub=False):
+    """Times exactly --steps steps after --warmup on one grid; returns the
+    JSON object of the result (the bench line's fields, or a sub-object)."""
+    kind, dtag, desc = WORKLOADS[workload]
+    nz, ny, nx = fields.shape
+    cells = nx * ny * nz
+    word = 8 if dtag == "f64" else 4
+    print(f"# {workload}: timing {args.steps} steps after {args.warmup} warmup", file=sys.stderr,
+          flush=True)
+    iord = OPTIONS.get(workload, {}).get("iord", 2)
+    div = OPTIONS.get(workload, {}).get("div", False)
+    g = time_gpu(fields, dtag, args.steps, args.warmup, args.tile, iord, div, args.ci_target)
+    ms_per_step = g["ms"] / args.steps
+    value = cells * args.steps / (g["ms"] / 1e3)
+    roof, valu = roofline(workload, fields.shape, word, ms_per_step)
+
+    from paper_1507_01265_amd import _lib
+    tile = args.tile or _lib.mpdata_default_tile(
+        _lib.MPDATA_FP64 if dtag == "f64" else _lib.MPDATA_FP32, int(fields.bc))
+    tx, ty, threads = _lib.mpdata_tile_info(tile)
+    config = {"workload": desc, "nx": nx, "ny": ny, "nz": nz,
+              "bc": "periodic" if fields.bc == 0 else "open", "iord": iord, "nonos": True,
+              "divergent_flow_term": div,
+              "tile": tile, "output_tile": f"{tx}x{ty}", "threads_per_workgroup": threads}
+    head = {"value": value, "unit": "cell-updates/s", "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms_per_step, "dtype": dtag, "config": config} if sub else {
+        "metric": "MPDATA cell-updates/s per step",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtag,
+        "data": "synthetic (seeded generator, resident in HBM)",
+        "config": config}
+    return {
+        **head,
+        "roofline": roof,
+        **({"valu": valu} if valu else {}),
+        **({"chain": {"launches_per_step": iord - 1,
+                      "bytes_per_step_by_design": chain_bytes(fields.shape, word, iord),
+                      "achieved_by_design_GBs": chain_bytes(fields.shape, word, iord)
+                      / (ms_per_step / 1e3) / 1e9}} if iord > 2 else {}),
+        "step_time_spread": spread(g["per_step_ms"]),
+        **({"repeated": {**spread(g["rep_ms"], f"repetitions_of_{args.steps}_steps"),
+                         "ci_target": args.ci_target}} if len(g["rep_ms"]) >= 2 else {}),
+        "mass_drift": (g["mass1"] - g["mass0"]) / g["mass0"],
+        "psi_min": g["psi_min"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,7 +506,13 @@ def main():
     ap.add_argument("--workload", default="rotation-fp64", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", type=int, default=0, help="launch shape id (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the error check against the oracle (and with it the CPU baseline)")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="rotation-fp64: do not also time the FP32 grid")
+    ap.add_argument("--error-steps", type=int, default=0,
+                    help="steps of the error check (0 = min(--steps, the workload's configured "
+                         "run: 100 rotation, 50 streamfunction))")
     ap.add_argument("--ci-target", type=float, default=0.01,
                     help="after the timed steps, repeat them until the 95%% Student-t half-width "
                          "is within this fraction of the mean (at most 50 times; 0 = off)")
@@ -417,66 +568,38 @@ def main():
         return
     print(f"# generating {args.workload}", file=sys.stderr, flush=True)
     fields = make_fields(kind)
+    line = single_grid(args, args.workload, fields)
+    # the default workload also times the same grid in FP32 (the metric
+    # names both precisions), with its own roofline and errors
+    if args.workload == "rotation-fp64" and not args.no_fp32:
+        line["fp32"] = single_grid(args, "rotation-fp32", fields, sub=True)
     nz, ny, nx = fields.shape
     cells = nx * ny * nz
-    word = 8 if dtag == "f64" else 4
-
-    print(f"# timing {args.steps} steps after {args.warmup} warmup", file=sys.stderr, flush=True)
     iord = OPTIONS.get(args.workload, {}).get("iord", 2)
     div = OPTIONS.get(args.workload, {}).get("div", False)
-    g = time_gpu(fields, dtag, args.steps, args.warmup, args.tile, iord, div, args.ci_target)
-    ms_per_step = g["ms"] / args.steps
-    value = cells * args.steps / (g["ms"] / 1e3)
-    abytes = algorithmic_bytes(fields.shape, word)
-    achieved = abytes / (ms_per_step / 1e3) / 1e9
-
-    from paper_1507_01265_amd import _lib
-    tile = args.tile or _lib.mpdata_default_tile(
-        _lib.MPDATA_FP64 if dtag == "f64" else _lib.MPDATA_FP32, int(fields.bc))
-    tx, ty, threads = _lib.mpdata_tile_info(tile)
-
-    line = {
-        "metric": "MPDATA cell-updates/s per step",
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": dtag,
-        "data": "synthetic (seeded generator, resident in HBM)",
-        "config": {"workload": desc, "nx": nx, "ny": ny, "nz": nz,
-                   "bc": "periodic" if fields.bc == 0 else "open", "iord": iord, "nonos": True,
-                   "divergent_flow_term": div,
-                   "tile": tile, "output_tile": f"{tx}x{ty}", "threads_per_workgroup": threads},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
-                     "algorithmic_bytes_per_launch": abytes},
-        **({"chain": {"launches_per_step": iord - 1,
-                      "bytes_per_step_by_design": chain_bytes(fields.shape, word, iord),
-                      "achieved_by_design_GBs": chain_bytes(fields.shape, word, iord)
-                      / (ms_per_step / 1e3) / 1e9}} if iord > 2 else {}),
-        "step_time_spread": spread(g["per_step_ms"]),
-        **({"repeated": {**spread(g["rep_ms"], f"repetitions_of_{args.steps}_steps"),
-                         "ci_target": args.ci_target}} if len(g["rep_ms"]) >= 2 else {}),
-        "mass_drift": (g["mass1"] - g["mass0"]) / g["mass0"],
-        "psi_min": g["psi_min"],
-    }
-    if not args.no_cpu_baseline:
+    if not args.no_errors:
+        # errors of a fresh run of E steps against the oracle's E steps on the
+        # same inputs; the FP64 oracle run is also the CPU baseline sample
         import oracle
         if args.cpu_threads:
             oracle.set_threads(args.cpu_threads)
-        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        f64 = fields if dtag == "f64" else fields.astype("float32").as_f64()
-        steps, el = cpu_baseline(f64, args.cpu_budget, iord=iord, div=div)
-        line["cpu_baseline"] = {"value": cells * steps / el, "unit": "cell-updates/s",
-                                "cores": oracle.threads(), "kind": "oracle",
-                                "sample": f"{nx}x{ny}x{nz} {args.workload} inputs, {steps} FP64 "
-                                          f"steps of the whole grid, {el:.1f} s",
-                                "cpu_model": cpu_model()}
+        E = error_steps(args, kind)
+        subs = [(line, args.workload)] + ([(line["fp32"], "rotation-fp32")] if "fp32" in line else [])
+        for obj, wl in subs:
+            dtag = WORKLOADS[wl][1]
+            print(f"# errors: {wl}, {E} steps on the GPU and in the oracle", file=sys.stderr,
+                  flush=True)
+            got, drift = error_run(fields, dtag, E, iord, div)
+            f64 = fields if dtag == "f64" else fields.astype("float32").as_f64()
+            want, el = oracle_steps(f64, E, iord, div)
+            obj["errors"] = errors(got, want, drift, E)
+            if obj is line and not args.no_cpu_baseline:
+                line["cpu_baseline"] = {
+                    "value": cells * E / el, "unit": "cell-updates/s", "cores": oracle.threads(),
+                    "kind": "oracle",
+                    "sample": f"{nx}x{ny}x{nz} {args.workload} inputs, {E} FP64 steps of the "
+                              f"whole grid (the run the errors are taken against), {el:.1f} s",
+                    "cpu_model": cpu_model()}
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

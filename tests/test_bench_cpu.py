@@ -72,3 +72,54 @@ def test_committed_profiles_match_the_kernel():
     kernel source, so the benchmark line reports measured traffic."""
     for w in ("rotation-fp64", "rotation-fp32", "streamfunction-fp32"):
         assert bench.measured_traffic(w) is not None, w
+
+
+def _fake_profile(tmp_path, monkeypatch, **figs):
+    p = tmp_path / "prof.md"
+    p.write_text(f"kernel_source_sha256: {bench.kernel_source_sha()}\n" +
+                 "".join(f"{k}: {v}\n" for k, v in figs.items()))
+    monkeypatch.setattr(bench, "PROFILES", {"w": str(p)})
+
+
+def test_roofline_names_the_roof_closer_to_saturation(tmp_path, monkeypatch):
+    shape, word = (64, 256, 512), 8
+    abytes = bench.algorithmic_bytes(shape, word)
+    ms = 0.2                                       # 2.02 TB/s: 0.25 of the HBM roof
+    # VALU busy 0.6 of 1024 SIMDs x 2.4 GHz over 0.2 ms
+    quad = 0.6 * 1024 * 2.4e9 * 0.2e-3 / 4
+    _fake_profile(tmp_path, monkeypatch, traffic_bytes_per_launch=5e8,
+                  valu_insts_per_launch=5.6e7, valu_quad_cycles_per_launch=quad)
+    roof, valu = bench.roofline("w", shape, word, ms)
+    assert roof["bound"] == "alu" and abs(roof["frac"] - 0.6) < 1e-12
+    assert abs(roof["hbm"]["frac"] - abytes / 0.2e-3 / 8e12) < 1e-12
+    assert roof["traffic"] == 5e8
+    assert abs(valu["lane_insts_per_cell_step"] - 5.6e7 * 64 / (512 * 256 * 64)) < 1e-9
+    # a kernel whose VALU is idler than its HBM roof is reported against HBM
+    _fake_profile(tmp_path, monkeypatch, valu_quad_cycles_per_launch=quad / 10)
+    roof, valu = bench.roofline("w", shape, word, ms)
+    assert roof["bound"] == "hbm" and valu["frac"] < roof["frac"]
+    # no counters of the current source: HBM only
+    monkeypatch.setattr(bench, "PROFILES", {})
+    roof, valu = bench.roofline("w", shape, word, ms)
+    assert roof["bound"] == "hbm" and valu is None and roof["traffic"] is None
+
+
+def test_error_metrics():
+    import numpy as np
+    want = np.array([0.0, 1.0, 2.0, -4.0])
+    got = want + np.array([0.0, 1e-6, 0.0, -2e-6])
+    e = bench.errors(got, want, 3e-9, 7)
+    assert abs(e["rel_linf"] / (2e-6 / 4) - 1) < 1e-9
+    assert abs(e["rel_l2"] / (np.sqrt(5e-12) / np.sqrt(21)) - 1) < 1e-9
+    assert e["mass_drift"] == 3e-9 and e["steps"] == 7
+
+
+def test_error_steps_follow_the_configured_run():
+    import argparse
+    a = argparse.Namespace(error_steps=0, steps=20)
+    assert bench.error_steps(a, "rotation") == 20
+    a.steps = 300
+    assert bench.error_steps(a, "rotation") == 100
+    assert bench.error_steps(a, "streamfunction") == 50
+    a.error_steps = 3
+    assert bench.error_steps(a, "streamfunction") == 3
