@@ -70,6 +70,9 @@ def _load():
         lib.orc_step.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, dp,
                                  ctypes.POINTER(_Stages)]
         lib.orc_step.restype = ctypes.c_int
+        lib.orc_step_tv.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                    ctypes.POINTER(_Stages)]
+        lib.orc_step_tv.restype = ctypes.c_int
         lib.orc_run.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, ctypes.c_int]
         lib.orc_run.restype = ctypes.c_int
         lib.orc_mass.argtypes = [ctypes.c_long, dp, dp]
@@ -134,6 +137,41 @@ def step(psi, u1, u2, u3, h, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15,
     if rc:
         raise ValueError(f"oracle step failed ({rc})")
     return (out, arrays) if stages else out
+
+
+def step_tv(psi, u1, u2, u3, w1, w2, w3, h, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15,
+            vsign=False, div=False):
+    """One step with Courant numbers that change in time: u1..u3 at the
+    start of the step, w1..w3 at its end (the time-variation term of the
+    first corrective pass, see mpdata_oracle.c)."""
+    psi, u1, u2, u3, h = _inputs(psi, u1, u2, u3, h)
+    nz, ny, nx = psi.shape
+    w1 = _f64(w1, (nz, ny, nx + 1), "w1")
+    w2 = _f64(w2, (nz, ny + 1, nx), "w2")
+    w3 = _f64(w3, (nz + 1, ny, nx), "w3")
+    p = _params(psi.shape, bc, iord, nonos, eps, vsign, div)
+    out = np.empty_like(psi)
+    rc = _load().orc_step_tv(ctypes.byref(p), _ptr(psi), _ptr(u1), _ptr(u2), _ptr(u3),
+                             _ptr(w1), _ptr(w2), _ptr(w3), _ptr(h), _ptr(out), None)
+    if rc:
+        raise ValueError(f"oracle step failed ({rc})")
+    return out
+
+
+def run_tv(psi, levels, h, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15, vsign=False,
+           div=False, term=True):
+    """len(levels) - 1 steps; levels[s] = (u1, u2, u3) at time level s.  Step
+    s runs from level s to level s + 1 (with term=False each step holds the
+    Courant numbers of its start, the plain scheme)."""
+    out = np.ascontiguousarray(psi, dtype=np.float64).copy()
+    for s in range(len(levels) - 1):
+        a, b = levels[s], levels[s + 1]
+        if term:
+            out = step_tv(out, *a, *b, h, bc=bc, iord=iord, nonos=nonos, eps=eps, vsign=vsign,
+                          div=div)
+        else:
+            out = step(out, *a, h, bc=bc, iord=iord, nonos=nonos, eps=eps, vsign=vsign, div=div)
+    return out
 
 
 def run(psi, u1, u2, u3, h, nsteps, *, bc=BC_PERIODIC, iord=2, nonos=True, eps=1e-15,

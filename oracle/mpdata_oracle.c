@@ -64,6 +64,20 @@
  * cyclic order).  In a later pass the velocity field is the previous pass's
  * antidiffusive velocity, which is divergent in general.
  *
+ * Option time-dependent velocity (orc_step_tv; the generalised MPDATA of the
+ * literature the paper cites, for flows that change in time): the step from
+ * level n to n+1 is given the Courant numbers at both levels, U at n (which
+ * the donor-cell pass and every other term use) and W at n+1.  Holding U at
+ * level n over the step leaves a first-order error, the flux
+ * (1/2) dt (dU/dt) psi, on every face; the first corrective pass takes it
+ * back with the term
+ *   +(1/2) (W - U)
+ * added to the pseudo-velocity of every face (after the divergent-flow term,
+ * before the limiter), zero on boundary-normal faces of an open domain like
+ * the rest of V.  Later corrective passes (iord > 2) correct their own pass,
+ * whose velocity does not change within the step, and add nothing.  With
+ * W = U the term is an exact zero.
+ *
  * Layout: cell arrays are [k][j][i] with i fastest, nx*ny*nz doubles.
  * Face arrays hold n+1 faces along their own axis: u1[k][j][i'] with
  * i' = 0..nx (face i' lies between cells i'-1 and i'), u2[k][j'][i],
@@ -309,6 +323,45 @@ static void pseudo_velocities(const grid *g, const double *p, const double *u1,
             }
 }
 
+/* ------------------------------------------- S3': time-variation term
+ * V_d += (W_d - U_d) / 2 on every face of every axis: W are the Courant
+ * numbers at the end of the step, U those at its start (option
+ * time-dependent velocity).  Boundary-normal faces of an open domain keep
+ * V = 0. */
+static void time_variation_term(const grid *g, const double *u1, const double *u2,
+                                const double *u3, const double *w1, const double *w2,
+                                const double *w3, double *v1, double *v2, double *v3)
+{
+    const int open = g->bc == ORC_BC_OPEN;
+    int k;
+#pragma omp parallel for schedule(static)
+    for (k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int f = 0; f <= g->nx; ++f) {
+                if (open && (f == 0 || f == g->nx)) continue;
+                long o = xface(g, f, j, k);
+                v1[o] = v1[o] + 0.5 * (w1[o] - u1[o]);
+            }
+#pragma omp parallel for schedule(static)
+    for (k = 0; k < g->nz; ++k)
+        for (int f = 0; f <= g->ny; ++f)
+            for (int i = 0; i < g->nx; ++i) {
+                if (open && (f == 0 || f == g->ny)) continue;
+                long o = yface(g, i, f, k);
+                v2[o] = v2[o] + 0.5 * (w2[o] - u2[o]);
+            }
+    int f;
+#pragma omp parallel for schedule(static)
+    for (f = 0; f <= g->nz; ++f) {
+        if (open && (f == 0 || f == g->nz)) continue;
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                long o = zface(g, i, j, f);
+                v3[o] = v3[o] + 0.5 * (w3[o] - u3[o]);
+            }
+    }
+}
+
 /* ------------------------------------------------------------ S4: bounds
  * mx_c (mn_c) is the maximum (minimum), over the cell and its six face
  * neighbours, of every field in fields[0 .. nf-1] -- the paper's stage 8
@@ -437,7 +490,16 @@ int orc_step(const orc_params *p, const double *psi, const double *u1,
              const double *u2, const double *u3, const double *h, double *out,
              orc_stages *st)
 {
+    return orc_step_tv(p, psi, u1, u2, u3, 0, 0, 0, h, out, st);
+}
+
+int orc_step_tv(const orc_params *p, const double *psi, const double *u1,
+                const double *u2, const double *u3, const double *w1,
+                const double *w2, const double *w3, const double *h, double *out,
+                orc_stages *st)
+{
     if (orc_check(p)) return -1;
+    if ((w1 != 0) != (w2 != 0) || (w1 != 0) != (w3 != 0)) return -1;
     grid g = {p->nx, p->ny, p->nz, p->bc};
     long n = (long)p->nx * p->ny * p->nz;
     long n1 = (long)(p->nx + 1) * p->ny * p->nz;
@@ -485,6 +547,8 @@ int orc_step(const orc_params *p, const double *psi, const double *u1,
         } else {
             pseudo_velocities(&g, cur, c1, c2, c3, h, p->eps, p->div, v[0], v[1], v[2]); /* S3 */
         }
+        if (k == 1 && w1)                                                   /* S3' */
+            time_variation_term(&g, u1, u2, u3, w1, w2, w3, v[0], v[1], v[2]);
         const int last = k == npass;
         if (last && st && st->v1) memcpy(st->v1, v[0], sizeof(double) * n1);
         if (last && st && st->v2) memcpy(st->v2, v[1], sizeof(double) * n2);

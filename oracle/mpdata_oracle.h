@@ -42,6 +42,15 @@ int orc_step(const orc_params *p, const double *psi, const double *u1,
              const double *u2, const double *u3, const double *h, double *out,
              orc_stages *stages);
 
+/* One step with Courant numbers that change in time: u1..u3 at the start of
+ * the step (level n), w1..w3 at its end (level n+1).  The first corrective
+ * pass adds (w - u)/2 to the pseudo-velocity of every face (zero on the
+ * boundary-normal faces of an open domain).  w1..w3 all NULL: orc_step. */
+int orc_step_tv(const orc_params *p, const double *psi, const double *u1,
+                const double *u2, const double *u3, const double *w1,
+                const double *w2, const double *w3, const double *h, double *out,
+                orc_stages *stages);
+
 /* nsteps steps in place on psi. */
 int orc_run(const orc_params *p, double *psi, const double *u1, const double *u2,
             const double *u3, const double *h, int nsteps);

@@ -1,6 +1,6 @@
 """Exact-rational derivation of the golden values of a 4-cell MPDATA line.
 
-Writes ``hand_1d.json`` and ``hand_div_1d.json`` beside this file (or, with
+Writes ``hand_1d.json``, ``hand_div_1d.json`` and ``hand_tv_1d.json`` beside this file (or, with
 ``--check``, compares what it derives with them).  Python's ``fractions``
 only; nothing here imports the oracle or the library, so the stored values
 are independent of both.
@@ -15,7 +15,9 @@ paper defers to in section 5.2:
   upper and lower face fluxes;
 * antidiffusive pseudo-velocity on a line (the cross terms vanish with no
   transverse flow): V = (|U| - U^2/G) (p_b - p_a)/(p_b + p_a), with the
-  divergent-flow term -(1/4)(U/G)(U_{f+1} - U_{f-1}) when asked for;
+  divergent-flow term -(1/4)(U/G)(U_{f+1} - U_{f-1}) when asked for, and
+  with Courant numbers that change over the step (U at its start, W at its
+  end) the time-variation term (W - U)/2 in the first corrective pass;
 * non-oscillatory limiter (Smolarkiewicz & Grabowski 1990): bounds over the
   3-point neighbourhood of psi^n and every iterate of the step, factors
   beta_up = (mx - p) h / IN and beta_dn = (p - mn) h / OUT from the
@@ -109,14 +111,18 @@ def limit(p, v, iterates):
     return out
 
 
-def step(p0, u, iord=2, nonos=True, div=False):
+def step(p0, u, iord=2, nonos=True, div=False, w=None):
     """One MPDATA step; returns (psi1, [V of each corrective pass before
-    limiting], result)."""
+    limiting], result).  w: the face Courant numbers at the end of the step
+    (time-dependent velocity; u holds those at its start): the first
+    corrective pass adds (w - u)/2 to every face's pseudo-velocity."""
     its = [list(p0), donor_pass(p0, u)]
     vel, vs = u, []
-    for _ in range(iord - 1):
+    for j in range(iord - 1):
         cur = its[-1]
         v = pseudo_velocity(cur, vel, div)
+        if w is not None and j == 0:
+            v = [v[f] + (w[f] - u[f]) / 2 for f in range(len(v))]
         vs.append(v)
         if nonos:
             v = limit(cur, v, its)
@@ -185,7 +191,38 @@ def derive_hand_div_1d():
     }
 
 
-FILES = {"hand_1d.json": derive_hand_1d, "hand_div_1d.json": derive_hand_div_1d}
+def derive_hand_tv_1d():
+    u = [Fr(1, 2)] * 5
+    w = [Fr(3, 4), Fr(1, 2), Fr(5, 8), Fr(1, 4), Fr(3, 4)]
+    cases = []
+    for name, p0 in (("donor_then_corrective", [1, 2, 3, 4]), ("limiter_step", [0, 0, 1, 1])):
+        p0 = [Fr(x) for x in p0]
+        psi1, vs, psi_free = step(p0, u, nonos=False, w=w)
+        _, _, psi_nonos = step(p0, u, nonos=True, w=w)
+        _, vs3, psi3_free = step(p0, u, iord=3, nonos=False, w=w)
+        cases.append({"name": name, "psi0": _s(p0), "psi1": _s(psi1),
+                      "v1_faces_0_to_4": _s(vs[0]), "psi_no_limiter": _s(psi_free),
+                      "psi_nonos": _s(psi_nonos),
+                      "v_pass2_no_limiter_faces_0_to_4": _s(vs3[1]),
+                      "psi_iord3_no_limiter": _s(psi3_free)})
+    return {
+        "source": "Exact rational values derived by the committed script tests/golden/derive_1d.py "
+                  "(Python fractions, eps taken in its limit 0+) for the time-variation term of "
+                  "the antidiffusive pseudo-velocity: a 4-cell periodic line, h = 1, face Courant "
+                  "numbers u1 = 1/2 at the start of the step and w1 (uneven, face 4 = face 0) at "
+                  "its end. The donor-cell pass and the standard pseudo-velocity take u1; the first "
+                  "corrective pass adds (w1 - u1)/2 on every face (holding u1 over the step leaves "
+                  "the first-order flux (1/2) dt (du/dt) psi, which the term takes back); a second "
+                  "corrective pass (iord 3) corrects its own pass and adds nothing. The limiter is "
+                  "the one of hand_1d.json.",
+        "u1_faces_0_to_4": _s(u),
+        "w1_faces_0_to_4": _s(w),
+        "cases": cases,
+    }
+
+
+FILES = {"hand_1d.json": derive_hand_1d, "hand_div_1d.json": derive_hand_div_1d,
+         "hand_tv_1d.json": derive_hand_tv_1d}
 
 
 def main(argv):

@@ -49,6 +49,12 @@ MUTANTS = {
                            u1[xface(g, fres(f - 1, g->nx, bc), j, k)]) +""",
         """                    dv = ((u1[xface(g, fres(f + 1, g->nx, bc), j, k)] -
                            u1[xface(g, fres(f - 1, g->nx, bc), j, k)]) + 0.0 * """),
+    "tv_term_sign": ("v1[o] = v1[o] + 0.5 * (w1[o] - u1[o]);", "v1[o] = v1[o] - 0.5 * (w1[o] - u1[o]);"),
+    "tv_term_factor": ("v1[o] = v1[o] + 0.5 * (w1[o] - u1[o]);", "v1[o] = v1[o] + (w1[o] - u1[o]);"),
+    "tv_term_every_pass": ("if (k == 1 && w1)", "if (w1)"),
+    "tv_term_no_z": ("v3[o] = v3[o] + 0.5 * (w3[o] - u3[o]);", "v3[o] = v3[o];"),
+    "tv_donor_pass_at_end_level": ("donor_cell_pass(&g, psi, u1, u2, u3, h, own[1]);",
+                                   "donor_cell_pass(&g, psi, w1 ? w1 : u1, w1 ? w2 : u2, w1 ? w3 : u3, h, own[1]);"),
     "vsign_in_corrective_pass": ("donor_cell_pass(&g, cur, v[0], v[1], v[2], h, own[k + 1]);",
                                  "donor_cell_pass(&g, p->vsign ? a1 : cur, v[0], v[1], v[2], h, own[k + 1]);"),
 }
@@ -77,6 +83,9 @@ def _checks():
     out["div_hand"] = lambda: pins.test_divergence_term_by_hand(oracle)
     out["div_order_1d"] = lambda: pins.test_divergence_term_restores_second_order_1d(oracle, 2)
     out["div_2d"] = lambda: pins.test_divergence_term_transverse_parts_2d(oracle)
+    out["tv_hand"] = lambda: pins.test_time_term_by_hand(oracle)
+    out["tv_order_1d"] = lambda: pins.test_time_term_restores_second_order_1d(oracle, 0.0)
+    out["tv_order_3d"] = lambda: pins.test_time_term_second_order_3d(oracle)
     return out
 
 

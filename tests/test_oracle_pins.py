@@ -657,3 +657,138 @@ def test_results_do_not_depend_on_the_thread_count(orc):
     np.testing.assert_array_equal(one, many)
     with pytest.raises(ValueError):
         orc.set_threads(0)
+
+
+# ------------------------------------ time-dependent velocity (step_tv)
+
+def test_time_term_by_hand(orc):
+    """4-cell line, Courant numbers 1/2 at the start of the step and uneven
+    ones at its end: the pseudo-velocity with the time-variation term and the
+    step with and without the limiter and with a second corrective pass,
+    against exact rationals (tests/golden/hand_tv_1d.json)."""
+    g = json.load(open(os.path.join(GOLDEN, "hand_tv_1d.json")))
+    u1 = _fr(g["u1_faces_0_to_4"]).reshape(1, 1, 5)
+    w1 = _fr(g["w1_faces_0_to_4"]).reshape(1, 1, 5)
+    z2, z3 = np.zeros((1, 2, 4)), np.zeros((2, 1, 4))
+    for c in g["cases"]:
+        psi = _fr(c["psi0"]).reshape(1, 1, 4)
+        args = (psi, u1, z2, z3, w1, z2, z3, np.ones((1, 1, 4)))
+        out = orc.step_tv(*args, nonos=False)
+        np.testing.assert_allclose(out.ravel(), _fr(c["psi_no_limiter"]), rtol=0, atol=1e-14)
+        out = orc.step_tv(*args, nonos=True)
+        np.testing.assert_allclose(out.ravel(), _fr(c["psi_nonos"]), rtol=0, atol=1e-14)
+        out = orc.step_tv(*args, nonos=False, iord=3)
+        np.testing.assert_allclose(out.ravel(), _fr(c["psi_iord3_no_limiter"]), rtol=0, atol=1e-14)
+
+
+def _ramp(s, S, C0, a):
+    """Courant number at time level s of a run of S steps: a quarter sine
+    from C0 to C0 (1 + a), so the end differs from the start."""
+    return C0 * (1 + a * np.sin(np.pi * s / (2 * S)))
+
+
+def _time_varying_1d_errors(orc, term, sizes, hvar=0.0, iord=2, C0=0.3, a=1.0):
+    """d(h psi)/dt + d(C(t) psi)/dx = 0 with a Courant number uniform in space
+    and rising in time: psi is constant along the characteristics, on which
+    the integral of h over x grows by the integral of C over t, D =
+    C0 S (1 + 2a/pi) after S steps."""
+    errs = []
+    for N in sizes:
+        S = int(round(N / 4 / C0))
+        x = np.arange(N) + 0.5
+        h = 1 + hvar * np.sin(2 * np.pi * x / N)
+        levels = [(np.full((1, 1, N + 1), _ramp(s, S, C0, a)), np.zeros((1, 2, N)),
+                   np.zeros((2, 1, N))) for s in range(S + 1)]
+        out = orc.run_tv((2 + np.sin(2 * np.pi * x / N)).reshape(1, 1, N), levels,
+                         h.reshape(1, 1, N), nonos=False, term=term, iord=iord)
+        D = C0 * S * (1 + 2 * a / np.pi)
+        H = lambda s: s - hvar * N / (2 * np.pi) * np.cos(2 * np.pi * s / N)
+        X0 = x - D
+        for _ in range(80):
+            X0 = X0 + (H(x) - H(X0) - D) / (1 + hvar * np.sin(2 * np.pi * X0 / N))
+        errs.append(np.abs(out.ravel() - (2 + np.sin(2 * np.pi * X0 / N))).max())
+    return np.array(errs)
+
+
+@pytest.mark.parametrize("hvar", [0.0, 0.3])
+def test_time_term_restores_second_order_1d(orc, hvar):
+    """Holding the Courant number of the start of the step over the step
+    shifts the solution by half the change of the Courant number over the
+    run: first order.  The time-variation term makes it second order (also
+    with variable h, where the term carries no face density)."""
+    e_on = _time_varying_1d_errors(orc, True, (64, 128, 256), hvar)
+    e_off = _time_varying_1d_errors(orc, False, (64, 128, 256), hvar)
+    assert np.all(e_on[:-1] / e_on[1:] > 3.5), e_on[:-1] / e_on[1:]
+    assert np.all(e_off[:-1] / e_off[1:] < 2.3), e_off[:-1] / e_off[1:]
+    assert e_on[-1] < 0.1 * e_off[-1]
+
+
+def test_time_term_second_order_3d(orc):
+    """Uniform oblique flow whose three components change in time by
+    different amounts: second order needs the term on every axis."""
+    C0 = np.array([0.2, -0.15, 0.1])
+    amp = np.array([1.0, 0.6, -0.8])
+
+    def err(N, term):
+        S = int(round(N / 4 / 0.25))
+        c = [np.arange(N) + 0.5] * 3
+        Z, Y, X = np.meshgrid(*c, indexing="ij")
+        prof = lambda X, Y, Z: (2 + np.sin(2 * np.pi * X / N) * np.cos(2 * np.pi * Y / N)
+                                * np.cos(2 * np.pi * Z / N))
+        levels = []
+        for s in range(S + 1):
+            cs = _ramp(s, S, C0, amp)
+            levels.append((np.full((N, N, N + 1), cs[0]), np.full((N, N + 1, N), cs[1]),
+                           np.full((N + 1, N, N), cs[2])))
+        out = orc.run_tv(prof(X, Y, Z), levels, np.ones((N, N, N)), nonos=False, term=term)
+        D = C0 * S * (1 + 2 * amp / np.pi)
+        return np.abs(out - prof(X - D[0], Y - D[1], Z - D[2])).max()
+    e = [err(N, True) for N in (32, 64)]
+    f = [err(N, False) for N in (32, 64)]
+    assert e[0] / e[1] > 3.6, e
+    assert f[0] / f[1] < 2.5, f
+    assert e[1] < 0.4 * f[1]
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("opts", [{}, {"div": True}, {"vsign": True}, {"iord": 3}],
+                         ids=["plain", "div", "vsign", "iord3"])
+def test_time_term_vanishes_for_steady_flow(orc, bc, opts):
+    """With the same Courant numbers at both ends of the step the term adds
+    exact zeros: bitwise the plain step."""
+    f = inputs.random_smooth(71, (6, 10, 14), bc=bc, cmax=0.25)
+    a = orc.step(f.psi, f.u1, f.u2, f.u3, f.h, bc=bc, **opts)
+    b = orc.step_tv(f.psi, f.u1, f.u2, f.u3, f.u1, f.u2, f.u3, f.h, bc=bc, **opts)
+    np.testing.assert_array_equal(a, b)
+
+
+def _two_levels(seed, shape, bc, cmax=0.2, divergence_free=False):
+    f = inputs.random_smooth(seed, shape, bc=bc, cmax=cmax, divergence_free=divergence_free)
+    g = inputs.random_smooth(seed + 1, shape, bc=bc, cmax=cmax, divergence_free=divergence_free)
+    return f, (g.u1, g.u2, g.u3)
+
+
+def test_time_term_conserves_mass_and_positivity(orc):
+    """Periodic: the term is a flux, so mass stays conserved to rounding.
+    With divergence-free Courant numbers at both ends psi is constant along
+    the characteristics, and with the limiter the step stays positive and
+    makes no new extrema."""
+    f, w = _two_levels(72, (8, 12, 16), 0, divergence_free=True)
+    psi = np.where(f.psi > f.psi.mean(), f.psi, 0.0)
+    out = orc.step_tv(psi, f.u1, f.u2, f.u3, *w, f.h)
+    m0, m1 = orc.mass(psi, f.h), orc.mass(out, f.h)
+    assert abs(m1 - m0) / m0 < 1e-14
+    assert out.min() >= -4 * U * psi.max()
+    assert out.max() <= psi.max() * (1 + 4 * U)
+    assert not np.array_equal(out, orc.step(psi, f.u1, f.u2, f.u3, f.h))
+
+
+def test_time_term_is_zero_on_open_boundary_faces(orc):
+    """Open boundaries: the pseudo-velocity normal to the boundary stays zero
+    with the term, so the mass budget is the first-order boundary flux of
+    the start-of-step Courant numbers."""
+    f, w = _two_levels(73, (6, 10, 12), 1)
+    out = orc.step_tv(f.psi, f.u1, f.u2, f.u3, *w, f.h, bc=1)
+    d = orc.mass(out, f.h) - orc.mass(f.psi, f.h)
+    inflow = orc.open_inflow(f.psi, f.u1, f.u2, f.u3)
+    assert abs(d - inflow) < 1e-12 * orc.mass(f.psi, f.h)
