@@ -69,7 +69,8 @@ enum {
 
 enum { MPDATA_FP64 = 0, MPDATA_FP32 = 1 };
 /* flags: NO_GRAPH -- launch every step on its own instead of replaying a
- * captured graph of step launches.  VSIGN -- fields of variable sign: the
+ * captured graph of step launches (a graph is otherwise built at creation).
+ * VSIGN -- fields of variable sign: the
  * ratios of the antidiffusive pseudo-velocity take |psi1| in place of psi1
  * (the variable-sign option of the MPDATA literature the paper cites,
  * Smolarkiewicz & Margolin 1998).  DIV -- flows that are not divergence-free:
@@ -77,8 +78,11 @@ enum { MPDATA_FP64 = 0, MPDATA_FP32 = 1 };
  * centred divergence of the pass's velocity field across the face
  * (Smolarkiewicz 1984); on a discretely divergence-free flow it adds exact
  * zeros.  VSIGN and DIV are built for the default launch shapes (tile 0, 2
- * or 5). */
-enum { MPDATA_FLAG_NO_GRAPH = 1, MPDATA_FLAG_VSIGN = 2, MPDATA_FLAG_DIV = 4 };
+ * or 5).  TVEL -- Courant numbers that change in time (single-grid contexts,
+ * iord 2, default launch shape, not with VSIGN): mpdata_step_tv advances the
+ * state with the Courant numbers given at both ends of every step; see
+ * there. */
+enum { MPDATA_FLAG_NO_GRAPH = 1, MPDATA_FLAG_VSIGN = 2, MPDATA_FLAG_DIV = 4, MPDATA_FLAG_TVEL = 8 };
 enum { MPDATA_BC_PERIODIC = 0, MPDATA_BC_OPEN = 1 }; /* OPEN = zero gradient */
 
 typedef struct {
@@ -139,9 +143,33 @@ int mpdata_create(const mpdata_params *p, void *psi, const void *u1, const void 
  * fused kernel over a plan of (tile, z-range) segments balanced across the
  * GPU (iord 2), or a chain of iord - 1 launches of it over the same plan
  * (iord > 2: the fused step, then one launch per further corrective pass).
- * Runs of 8 steps are replayed from a hipGraph built on first use (unless
- * MPDATA_FLAG_NO_GRAPH). */
+ * Runs of 8 steps are replayed from a hipGraph built by mpdata_create
+ * (unless MPDATA_FLAG_NO_GRAPH). */
 int mpdata_step(mpdata_ctx *ctx, int32_t nsteps);
+
+/* Time steps with Courant numbers that change in time (a context created
+ * with MPDATA_FLAG_TVEL; MPDATA_ENOTSUP otherwise).  The velocity bound to
+ * the context (u1, u2, u3 of mpdata_create, or the last level of the
+ * previous call) is the level at the start of the first step; u1[s], u2[s],
+ * u3[s] (host arrays of nsteps device pointers, each array laid out as at
+ * mpdata_create) are the levels at the end of step s, so step s runs from
+ * level s to level s + 1.  Every stage of a step uses the Courant numbers
+ * of its start; holding them over the step leaves a first-order error, the
+ * flux (1/2) dt (dU/dt) psi, which the first corrective pass takes back by
+ * adding (U(end) - U(start)) / 2 to the antidiffusive pseudo-velocity of
+ * every face (zero on the boundary-normal faces of an open domain).  This
+ * is the time-dependent-flow correction of the generalised MPDATA of the
+ * literature the paper cites (section 5.2 defers the scheme to it); with
+ * equal levels it adds exact zeros.  Ownership: the caller keeps every level
+ * alive until the steps that read it have run; afterwards the last level is
+ * bound to the context (read by later steps, mpdata_step included, which
+ * holds it over each step) until the next call.  Each level's periodic face
+ * pairs are checked on the stream: a mismatch is reported by the next
+ * mpdata_sync or mpdata_mass as MPDATA_EINVAL (the steps that used the level
+ * have run).  An odd step count ends with one device copy into psi, as in
+ * mpdata_step; the steps are launched one by one (no graph). */
+int mpdata_step_tv(mpdata_ctx *ctx, int32_t nsteps, const void *const *u1, const void *const *u2,
+                   const void *const *u3);
 
 /* Mass M = sum over cells of h*psi with a compensated (double-double)
  * reduction: wave-level and block-level partials, then one deterministic
@@ -153,7 +181,8 @@ int mpdata_mass(mpdata_ctx *ctx, double *out);
 int mpdata_get_psi(mpdata_ctx *ctx, void *dst_device);
 int mpdata_set_psi(mpdata_ctx *ctx, const void *src_device);
 
-/* Waits for all work enqueued by this context. */
+/* Waits for all work enqueued by this context (MPDATA_EINVAL if a time level
+ * given to mpdata_step_tv broke periodicity). */
 int mpdata_sync(mpdata_ctx *ctx);
 
 /* Number of time steps executed since creation (or the last set_psi). */

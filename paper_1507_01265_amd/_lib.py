@@ -27,6 +27,7 @@ MPDATA_BC_OPEN = 1
 MPDATA_FLAG_NO_GRAPH = 1
 MPDATA_FLAG_VSIGN = 2
 MPDATA_FLAG_DIV = 4
+MPDATA_FLAG_TVEL = 8
 
 ERRORS = {MPDATA_EINVAL: "EINVAL", MPDATA_ENOMEM: "ENOMEM", MPDATA_EDEVICE: "EDEVICE",
           MPDATA_ENOTSUP: "ENOTSUP", MPDATA_ENONFINITE: "ENONFINITE"}
@@ -73,6 +74,9 @@ _SIGNATURES = {
                        ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
                       ctypes.c_int),
     "mpdata_step": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int),
+    "mpdata_step_tv": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)],
+                       ctypes.c_int),
     "mpdata_mass": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "mpdata_get_psi": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "mpdata_set_psi": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -216,6 +220,16 @@ def mpdata_create(params, psi, u1, u2, u3, h, workspace, ws_bytes, stream):
 
 def mpdata_step(ctx, nsteps: int):
     check(load().mpdata_step(ctx, nsteps), ctx)
+
+
+def mpdata_step_tv(ctx, u1, u2, u3):
+    """len(u1) steps; u1[s], u2[s], u3[s] are device pointers of the Courant
+    numbers at the end of step s."""
+    n = len(u1)
+    if len(u2) != n or len(u3) != n:
+        raise ValueError("u1, u2, u3 need one pointer per step each")
+    vp = lambda xs: (ctypes.c_void_p * max(n, 1))(*xs)
+    check(load().mpdata_step_tv(ctx, n, vp(u1), vp(u2), vp(u3)), ctx)
 
 
 def mpdata_mass(ctx) -> float:

@@ -79,7 +79,7 @@ const char *check_params(const mpdata_params *p)
     // h eps^3 on a zero background and the limiter's (IN + eps)(OUT + eps)
     // about eps^2: eps >= 1e-30 keeps both normal
     if (!(p->eps >= 1e-30) || !isfinite(p->eps)) return "eps must be finite and >= 1e-30";
-    if (p->flags & ~(MPDATA_FLAG_NO_GRAPH | MPDATA_FLAG_VSIGN | MPDATA_FLAG_DIV))
+    if (p->flags & ~(MPDATA_FLAG_NO_GRAPH | MPDATA_FLAG_VSIGN | MPDATA_FLAG_DIV | MPDATA_FLAG_TVEL))
         return "unknown flag bits";
     if (p->reserved != 0) return "reserved must be 0";
     int count = 0;
@@ -91,6 +91,13 @@ const char *check_params(const mpdata_params *p)
         (shape_of(p->tile).rx != 32 || (shape_of(p->tile).ry != 24 && shape_of(p->tile).ry != 32)))
         return "the variable-sign option and the divergent-flow term run on the 32x24 and 32x32 "
                "launch shapes (tile 0, 2 or 5)";
+    if (p->flags & MPDATA_FLAG_TVEL) {
+        if (p->iord != 2) return "Courant numbers that change in time (MPDATA_FLAG_TVEL) need iord 2";
+        if (p->flags & MPDATA_FLAG_VSIGN)
+            return "MPDATA_FLAG_TVEL does not combine with the variable-sign option";
+        if (p->tile != 0 && p->tile != default_tile(p->dtype, p->bc))
+            return "MPDATA_FLAG_TVEL runs on the default launch shape (tile 0)";
+    }
     return nullptr;
 }
 
@@ -339,7 +346,8 @@ int variant_of(const mpdata_params &p)
 {
     return (p.bc == MPDATA_BC_OPEN ? mpd::kVariantOpen : 0) | (p.nonos ? mpd::kVariantNonos : 0) |
            ((p.flags & MPDATA_FLAG_VSIGN) ? mpd::kVariantVsign : 0) |
-           ((p.flags & MPDATA_FLAG_DIV) ? mpd::kVariantDiv : 0);
+           ((p.flags & MPDATA_FLAG_DIV) ? mpd::kVariantDiv : 0) |
+           ((p.flags & MPDATA_FLAG_TVEL) ? mpd::kVariantTvel : 0);
 }
 
 int wg_per_cu(int dtype, int tile, int variant)
@@ -372,6 +380,8 @@ void default_plan_bounds(const std::vector<mpdata_params> &grids, int tile, int 
 struct Engine {
     int dtype, tile, nwg, nseg, ngrids, iord;
     bool open, nonos, use_graph;
+    bool tvel = false;                         // Courant numbers that change in time
+    mpd::TvArgs<double> tv{};                  // TVEL: the bound level as both ends of a step
     int variant;  // kernel variant bits (open, nonos, variable sign)
     double eps;
     hipStream_t stream;
@@ -391,6 +401,21 @@ static int fail_to(char *dst, int code, const char *fmt, ...)
     vsnprintf(dst, 256, fmt, ap);
     va_end(ap);
     return code;
+}
+
+// One launch of the fused step kernel over the engine's plan; tv: the time
+// levels of the Courant numbers (read by the TVEL variant only).
+static hipError_t launch_step(Engine &e, int flip, long long *ticks, const mpd::TvArgs<double> &tv)
+{
+    const mpd::Segment *segs = (const mpd::Segment *)(e.ws + e.lay.segs);
+    const int *wg = (const int *)(e.ws + e.lay.wg);
+    if (e.dtype == MPDATA_FP32)
+        return mpd::launch_persistent<float>((const mpd::GridDesc<float> *)(e.ws + e.lay.grids),
+                                             segs, wg, e.nwg, e.tile, e.variant, flip,
+                                             e.eps, ticks, (const mpd::TvArgs<float> &)tv, e.stream);
+    return mpd::launch_persistent<double>((const mpd::GridDesc<double> *)(e.ws + e.lay.grids),
+                                          segs, wg, e.nwg, e.tile, e.variant, flip, e.eps,
+                                          ticks, tv, e.stream);
 }
 
 static hipError_t launch_one(Engine &e, int flip, long long *ticks)
@@ -428,13 +453,7 @@ static hipError_t launch_one(Engine &e, int flip, long long *ticks)
         }
         return hipSuccess;
     }
-    if (e.dtype == MPDATA_FP32)
-        return mpd::launch_persistent<float>((const mpd::GridDesc<float> *)(e.ws + e.lay.grids),
-                                             segs, wg, e.nwg, e.tile, e.variant, flip,
-                                             e.eps, ticks, e.stream);
-    return mpd::launch_persistent<double>((const mpd::GridDesc<double> *)(e.ws + e.lay.grids),
-                                          segs, wg, e.nwg, e.tile, e.variant, flip, e.eps,
-                                          ticks, e.stream);
+    return launch_step(e, flip, ticks, e.tv);
 }
 
 // Graph of kGraphSteps steps (each launch reading what the previous wrote):
@@ -477,10 +496,11 @@ static hipError_t build_graph(Engine &e)
         return hipGraphInstantiate(&e.graph, e.graph_def, nullptr, nullptr, 0);
     }
     int flips[kGraphSteps];
+    mpd::TvArgs<double> tv = e.tv;  // TVEL contexts: the bound level, held over each step
     for (int s = 0; s < kGraphSteps; ++s) {
         flips[s] = s & 1;
         void *args[] = {(void *)&gridp, (void *)&segp, (void *)&wgp, (void *)&flips[s],
-                        (void *)&e.eps, (void *)&no_ticks};
+                        (void *)&e.eps, (void *)&no_ticks, (void *)&tv};
         hipKernelNodeParams kp{};
         kp.func = (void *)(e.dtype == MPDATA_FP32 ? mpd::step_kernel_ptr<float>(e.tile, e.variant)
                                                   : mpd::step_kernel_ptr<double>(e.tile, e.variant));
@@ -534,6 +554,41 @@ static int engine_step(Engine &e, int32_t nsteps)
     return MPDATA_OK;
 }
 
+// Builds the replay graph ahead of the first run of steps, so that a run's
+// first steps do not pay for its instantiation; a failed build leaves plain
+// launches of the same kernel.
+static void engine_prepare_graph(Engine &e)
+{
+    if (!e.use_graph || e.iord < 2 || e.graph) return;
+    if (build_graph(e) != hipSuccess) {
+        e.use_graph = false;
+        if (e.graph) (void)hipGraphExecDestroy(e.graph);
+        if (e.graph_def) (void)hipGraphDestroy(e.graph_def);
+        e.graph = nullptr;
+        e.graph_def = nullptr;
+        (void)hipGetLastError();
+    }
+}
+
+// TVEL contexts: later time levels are checked on the stream (periodic face
+// pairs into flags[2]); a nonzero count is reported once the stream is
+// synchronised.
+static int engine_tv_status(Engine &e)
+{
+    if (!e.tvel || e.params[0].bc != MPDATA_BC_PERIODIC) return MPDATA_OK;
+    unsigned int bad = 0;
+    hipError_t r = hipMemcpyAsync(&bad, (unsigned int *)(e.ws + e.lay.flags) + 2, sizeof(bad),
+                                  hipMemcpyDeviceToHost, e.stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(e.stream);
+    if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "level check readback: %s", hipGetErrorString(r));
+    if (bad)
+        return fail_to(e.err, MPDATA_EINVAL,
+                       "a time level given to mpdata_step_tv breaks periodicity (%u face pairs with "
+                       "face n != face 0); the steps that used it have run",
+                       bad);
+    return MPDATA_OK;
+}
+
 static int engine_mass(Engine &e, int i, double *out)
 {
     double *parts = (double *)(e.ws + e.lay.partials);
@@ -551,7 +606,7 @@ static int engine_mass(Engine &e, int i, double *out)
     if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "mass readback: %s", hipGetErrorString(r));
     *out = h2[0];
     if (!isfinite(h2[0])) return fail_to(e.err, MPDATA_ENONFINITE, "psi holds NaN or Inf");
-    return MPDATA_OK;
+    return engine_tv_status(e);
 }
 
 // Descriptors of the chain of corrective passes (iord > 2) for both step
@@ -627,6 +682,9 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
     }
     if (batch && params[0].iord != 2)
         return fail_to(errbuf, MPDATA_ENOTSUP, "batches run the full step (iord 2)");
+    if (batch && (params[0].flags & MPDATA_FLAG_TVEL))
+        return fail_to(errbuf, MPDATA_ENOTSUP,
+                       "Courant numbers that change in time run on single-grid contexts");
     if (!workspace) return fail_to(errbuf, MPDATA_EINVAL, "NULL array or workspace pointer");
     if (((uintptr_t)workspace & (kAlign - 1)) != 0)
         return fail_to(errbuf, MPDATA_EINVAL, "workspace must be 256-byte aligned");
@@ -639,6 +697,7 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
     e.variant = variant_of(params[0]);
     e.eps = params[0].eps;
     e.use_graph = !(params[0].flags & MPDATA_FLAG_NO_GRAPH);
+    e.tvel = (params[0].flags & MPDATA_FLAG_TVEL) != 0;
     e.stream = (hipStream_t)stream;
     e.ngrids = n;
     e.ws = (char *)workspace;
@@ -716,6 +775,10 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
             return fail_to(errbuf, MPDATA_EINVAL,
                            "grid %d: periodic boundaries need face n == face 0 on every axis (%u differ)",
                            i, hf[1]);
+    }
+    if (e.tvel) {
+        const mpd::GridDesc<double> &g = e.grids[0];
+        e.tv = mpd::TvArgs<double>{g.u1, g.u2, g.u3, g.u1, g.u2, g.u3};
     }
     // descriptors and plan into the workspace (GridDesc<float> has the same layout)
     r = hipMemcpyAsync(e.ws + e.lay.grids, e.grids.data(), n * sizeof(mpd::GridDesc<double>),
@@ -1006,6 +1069,7 @@ int mpdata_create(const mpdata_params *p, void *psi, const void *u1, const void 
         delete c;
         return rc;
     }
+    engine_prepare_graph(c->e);
     c->steps = 0;
     *out = c;
     return MPDATA_OK;
@@ -1047,12 +1111,72 @@ int mpdata_set_psi(mpdata_ctx *c, const void *src)
     return MPDATA_OK;
 }
 
+int mpdata_step_tv(mpdata_ctx *c, int32_t nsteps, const void *const *u1, const void *const *u2,
+                   const void *const *u3)
+{
+    if (!c) return MPDATA_EINVAL;
+    Engine &e = c->e;
+    if (!e.tvel)
+        return fail_to(e.err, MPDATA_ENOTSUP, "the context was created without MPDATA_FLAG_TVEL");
+    if (nsteps < 0) return fail_to(e.err, MPDATA_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return MPDATA_OK;
+    if (!u1 || !u2 || !u3) return fail_to(e.err, MPDATA_EINVAL, "NULL level list");
+    for (int32_t s = 0; s < nsteps; ++s) {
+        if (!u1[s] || !u2[s] || !u3[s])
+            return fail_to(e.err, MPDATA_EINVAL, "level %d: NULL array", (int)s + 1);
+        if (misaligned(u1[s]) || misaligned(u2[s]) || misaligned(u3[s]))
+            return fail_to(e.err, MPDATA_EINVAL, "level %d: arrays must be 16-byte aligned", (int)s + 1);
+    }
+    const mpdata_params &p = e.params[0];
+    hipError_t r = hipSuccess;
+    unsigned int *bad = (unsigned int *)(e.ws + e.lay.flags) + 2;
+    if (p.bc == MPDATA_BC_PERIODIC)
+        for (int32_t s = 0; s < nsteps && r == hipSuccess; ++s)
+            r = e.dtype == MPDATA_FP64
+                    ? mpd::launch_check_periodic_faces<double>((const double *)u1[s], (const double *)u2[s],
+                                                               (const double *)u3[s], p.nx, p.ny, p.nz,
+                                                               bad, e.stream)
+                    : mpd::launch_check_periodic_faces<float>((const float *)u1[s], (const float *)u2[s],
+                                                              (const float *)u3[s], p.nx, p.ny, p.nz,
+                                                              bad, e.stream);
+    if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "level check launch: %s", hipGetErrorString(r));
+    // step s runs from level s (the bound level for s = 0) to level s + 1
+    mpd::TvArgs<double> tv = e.tv;
+    for (int32_t s = 0; s < nsteps; ++s) {
+        tv.w1 = (const double *)u1[s];
+        tv.w2 = (const double *)u2[s];
+        tv.w3 = (const double *)u3[s];
+        r = launch_step(e, s & 1, nullptr, tv);
+        if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "step launch: %s", hipGetErrorString(r));
+        tv.u1 = tv.w1;
+        tv.u2 = tv.w2;
+        tv.u3 = tv.w3;
+    }
+    if (nsteps & 1) {
+        r = e.dtype == MPDATA_FP32
+                ? mpd::launch_copy_back<float>((const mpd::GridDesc<float> *)(e.ws + e.lay.grids), 1, e.stream)
+                : mpd::launch_copy_back<double>((const mpd::GridDesc<double> *)(e.ws + e.lay.grids), 1, e.stream);
+        if (r != hipSuccess) return fail_to(e.err, MPDATA_EDEVICE, "copy back: %s", hipGetErrorString(r));
+    }
+    // the last level is now the bound one: the replay graph of plain steps
+    // (which holds it over each step) is rebuilt for it
+    e.tv = mpd::TvArgs<double>{tv.u1, tv.u2, tv.u3, tv.u1, tv.u2, tv.u3};
+    e.grids[0].u1 = tv.u1;
+    e.grids[0].u2 = tv.u2;
+    e.grids[0].u3 = tv.u3;
+    engine_release(e);
+    engine_prepare_graph(e);
+    c->steps += nsteps;
+    return MPDATA_OK;
+}
+
 int mpdata_sync(mpdata_ctx *c)
 {
     if (!c) return MPDATA_EINVAL;
     hipError_t r = hipStreamSynchronize(c->e.stream);
-    return r == hipSuccess ? MPDATA_OK
-                           : fail_to(c->e.err, MPDATA_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(r));
+    if (r != hipSuccess)
+        return fail_to(c->e.err, MPDATA_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(r));
+    return engine_tv_status(c->e);
 }
 
 int64_t mpdata_steps_done(const mpdata_ctx *c) { return c ? c->steps : -1; }
@@ -1118,6 +1242,7 @@ int mpdata_batch_create(int32_t n, const mpdata_params *params, void *const *psi
         delete b;
         return rc;
     }
+    engine_prepare_graph(b->e);
     *out = b;
     return MPDATA_OK;
 }
@@ -1193,6 +1318,9 @@ int mpdata_pool_create(const mpdata_params *shared, int32_t max_grids, int32_t m
     sp.nx = sp.ny = sp.nz = 1;
     sp.iord = 2;
     if (const char *m = check_params(&sp)) return pool_fail(nullptr, MPDATA_EINVAL, "%s", m);
+    if (sp.flags & MPDATA_FLAG_TVEL)
+        return pool_fail(nullptr, MPDATA_ENOTSUP,
+                         "Courant numbers that change in time run on single-grid contexts");
     if (max_grids < 1 || max_segments < 1)
         return pool_fail(nullptr, MPDATA_EINVAL, "max_grids and max_segments must be >= 1");
     if (!workspace || ((uintptr_t)workspace & (kAlign - 1)) != 0)

@@ -40,8 +40,17 @@ struct TileShape {
 const TileShape *tile_shapes(int *count);
 
 // Kernel variants: open boundaries, limiter on, variable-sign option,
-// divergent-flow term.
-enum { kVariantOpen = 1, kVariantNonos = 2, kVariantVsign = 4, kVariantDiv = 8 };
+// divergent-flow term, Courant numbers that change in time.
+enum { kVariantOpen = 1, kVariantNonos = 2, kVariantVsign = 4, kVariantDiv = 8, kVariantTvel = 16 };
+
+// The two time levels of the Courant numbers of one step of a single grid
+// whose velocity changes in time (variant kVariantTvel): u at the start of
+// the step (level n, used by every stage) and w at its end (level n+1, used
+// only by the time-variation term of the pseudo-velocity).  Passed by value;
+// the other variants ignore it.
+template <typename T> struct TvArgs {
+    const T *u1, *u2, *u3, *w1, *w2, *w3;
+};
 
 // The persistent fused step kernel for (T, tile id, variant), as a function
 // pointer (for graph nodes and occupancy queries); nullptr if that variant is
@@ -51,7 +60,7 @@ template <typename T> const void *step_kernel_ptr(int tile, int variant);
 template <typename T>
 hipError_t launch_persistent(const GridDesc<T> *grids, const Segment *segs, const int *wg_begin,
                              int nwg, int tile, int variant, int flip, double eps,
-                             long long *seg_ticks, hipStream_t s);
+                             long long *seg_ticks, const TvArgs<T> &tv, hipStream_t s);
 
 // Launches of a chain of corrective passes (iord > 2), one grid each:
 // grids[0].psi[0] -> grids[0].psi[1] with the arrays of io[0].  mode is
@@ -84,6 +93,12 @@ hipError_t launch_copy_back(const GridDesc<T> *grids, int ngrids, hipStream_t s)
 template <typename T>
 hipError_t launch_mass(const T *psi, const T *h, size_t n, double *partials, int nparts,
                        double *result, hipStream_t s);
+
+// Counts (atomically, into *flags) the periodic face pairs (face n vs face
+// 0 along every axis) of u1, u2, u3 that differ bit for bit.
+template <typename T>
+hipError_t launch_check_periodic_faces(const T *u1, const T *u2, const T *u3, int nx, int ny,
+                                       int nz, unsigned int *flags, hipStream_t s);
 
 template <typename T>
 hipError_t launch_validate(const T *h, const T *u1, const T *u2, const T *u3, int nx, int ny,

@@ -281,12 +281,14 @@ template <typename T> __device__ __forceinline__ T from_hi(T v) { return dpp<kDp
 // y-faces and h (needed one iteration ahead) ...
 template <typename T> struct PlaneA {
     T u1lo, u1hi, u2lo, u2hi, h;
+    T w1lo, w2lo;  // the lower faces' Courant numbers at the end of the step (TVEL)
 };
 // ... and psi^n and the Courant number of its lower z-face (needed two
 // iterations ahead; in a further corrective pass also the two cell arrays
 // bx, bn that bound the earlier iterates).
 template <typename T> struct PlaneB {
     T pn, u3lo, bx, bn;
+    T w3lo;  // the lower z-face's Courant number at the end of the step (TVEL)
 };
 
 // ================================================================ fused step
@@ -336,12 +338,19 @@ template <typename T, int RX, int RY, int MODE, bool DIVP = false> struct Smem {
 // OPZ: open in z.  An open grid's tiles whose region and ring lie inside the
 // domain with a cell to spare (x_interior) run with OPXY false: there
 // clamping and wrapping are both the identity and no lane sits on a
-// boundary.
-template <typename T, int RX, int RY, bool OPXY, bool OPZ, bool NONOS, bool VSIGN, bool DIV, int MODE>
+// boundary.  TVEL: Courant numbers that change in time; g holds those of
+// the start of the step and tv.w1..w3 those of its end, and the pseudo-
+// velocity of every face gains the time-variation term (w - u)/2 (holding u
+// over the step leaves the first-order flux (1/2) dt (du/dt) psi, which the
+// term takes back).
+template <typename T, int RX, int RY, bool OPXY, bool OPZ, bool NONOS, bool VSIGN, bool DIV, int MODE,
+          bool TVEL = false>
 __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io, int flip, int tx,
                                       int ty, int z0, int z1, double eps_d,
-                                      Smem<T, RX, RY, MODE, DIV> &sm)
+                                      Smem<T, RX, RY, MODE, DIV> &sm,
+                                      const TvArgs<T> &tv = TvArgs<T>{})
 {
+    static_assert(!TVEL || MODE == kModeStep, "the time-variation term belongs to the fused step");
     constexpr bool kPass = MODE >= kModeMid;                      // S1 replaced by a load
     constexpr bool kOuts = MODE == kModeHead || MODE == kModeMid; // velocity + bounds out
     using L = double;  // limiter precision (both variants)
@@ -438,6 +447,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         const Rsrc u2p = plane_rsrc(g.u2, k, pc_u2);
         r.h = bload<T>(hp, b_c);
         r.u1lo = bload<T>(u1p, b_u1lo);
+        if constexpr (TVEL) {
+            r.w1lo = bload<T>(plane_rsrc(tv.w1, k, pc_u1), b_u1lo);
+            r.w2lo = bload<T>(plane_rsrc(tv.w2, k, pc_u2), OPXY ? b_u2lo : b_c);
+        }
         if (OPXY) {
             r.u1hi = bload<T>(u1p, b_u1hi);
             r.u2lo = bload<T>(u2p, b_u2lo);
@@ -456,6 +469,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         const Rsrc u3p = plane_rsrc(g.u3, kf, pc_cells);
         r.pn = bload<T>(pp, b_c);
         r.u3lo = bload<T>(u3p, b_c);
+        if constexpr (TVEL) r.w3lo = bload<T>(plane_rsrc(tv.w3, kf, pc_cells), b_c);
         if constexpr (kPass && NONOS) {
             r.bx = bload<T>(plane_rsrc(io.bmx, k, pc_cells), b_c);
             r.bn = bload<T>(plane_rsrc(io.bmn, k, pc_cells), b_c);
@@ -502,6 +516,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     // plane below it: the bounds at t-1 add only psi^n(t) to these
     T zmx_m1 = T(0), zmn_m1 = T(0);
     T u1_m1 = T(0), u2_m1 = T(0);               // lower-face Courant, plane t-1
+    T w1_m1 = T(0), w2_m1 = T(0);               // the same at the end of the step (TVEL)
     T rh_m1 = T(1), rh_m2 = T(1), rh_m3 = T(1); // 1/h of planes t-1 .. t-3
     // Own-column psi1 of planes t-1 .. t-3 and the Courant sums and h of plane
     // t-1 also sit in LDS (for the neighbours); the column keeps its own copy
@@ -696,6 +711,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                                           av(qyp_) + av(qyp_a), av(qym_) + av(qym_a), c3_a + c3_m1,
                                           av(p1_hi) + av(phi_a), av(p1_lo) + av(plo_a), eps,
                                           d_a + d_m1);
+                if constexpr (TVEL) v1 = v1 + T(0.5) * (w1_m1 - u1_m1);
                 if (zero_v1) v1 = T(0);
             }
             // the three faces are scheduled one after another: each face's
@@ -727,6 +743,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                                               av(qxp_) + av(qd_xp), av(qxm_) + av(qd_xm), eps,
                                               d_ya + d_m1);
                 }
+                if constexpr (TVEL) v2 = v2 + T(0.5) * (w2_m1 - u2_m1);
                 if (zero_v2) v2 = T(0);
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -758,6 +775,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                                           c2_m1 + c2_c, av(Qb[q + cyp]) + av(qyp_),
                                           av(Qb[q + cym]) + av(qym_), eps, d_m1 + d_c);
             }
+            if constexpr (TVEL) v3 = v3 + T(0.5) * (cur.w3lo - cur.u3lo);
             if (OZ && (t <= 0 || t >= nz)) v3 = T(0);
             if (NONOS) {
                 // ---- S4 bounds at plane p
@@ -870,6 +888,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         zmn_m1 = zmn_c;
         u1_m1 = curA.u1lo;
         u2_m1 = curA.u2lo;
+        if constexpr (TVEL) {
+            w1_m1 = curA.w1lo;
+            w2_m1 = curA.w2lo;
+        }
         rh_m3 = rh_m2;
         rh_m2 = rh_m1;
         rh_m1 = rh_c;

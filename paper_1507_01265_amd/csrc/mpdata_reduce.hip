@@ -147,6 +147,33 @@ __global__ __launch_bounds__(256) void validate(const T *__restrict__ h, const T
     if (bad_f) atomicAdd(&flags[1], bad_f);
 }
 
+// Periodic face pairs of a further time level of the Courant numbers:
+// thread r of the grid-stride loop takes pair r of the ny*nz x-pairs, then
+// the nz*nx y-pairs, then the ny*nx z-pairs.
+template <typename T>
+__global__ __launch_bounds__(256) void periodic_faces(const T *__restrict__ u1, const T *__restrict__ u2,
+                                                      const T *__restrict__ u3, int nx, int ny, int nz,
+                                                      unsigned int *__restrict__ flags)
+{
+    const size_t n1 = (size_t)ny * nz, n2 = (size_t)nz * nx, n3 = (size_t)ny * nx;
+    unsigned int bad = 0;
+    for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < n1 + n2 + n3;
+         r += (size_t)gridDim.x * blockDim.x) {
+        if (r < n1) {
+            const size_t o = r * (nx + 1);
+            bad += !same_bits(u1[o], u1[o + nx]);
+        } else if (r < n1 + n2) {
+            const size_t k = (r - n1) / nx, i = (r - n1) % nx;
+            const size_t o = k * (ny + 1) * nx + i;
+            bad += !same_bits(u2[o], u2[o + (size_t)ny * nx]);
+        } else {
+            const size_t o = r - n1 - n2;
+            bad += !same_bits(u3[o], u3[o + (size_t)nz * ny * nx]);
+        }
+    }
+    if (bad) atomicAdd(flags, bad);
+}
+
 // ================================================================ copy back
 // psi[1] -> psi[0] for every grid of a launch (ends an odd number of steps);
 // one workgroup row per grid.
@@ -195,6 +222,21 @@ hipError_t launch_validate(const T *h, const T *u1, const T *u2, const T *u3, in
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_check_periodic_faces(const T *u1, const T *u2, const T *u3, int nx, int ny,
+                                       int nz, unsigned int *flags, hipStream_t s)
+{
+    const size_t n = (size_t)ny * nz + (size_t)nz * nx + (size_t)ny * nx;
+    const int blocks = (int)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    periodic_faces<T><<<blocks, 256, 0, s>>>(u1, u2, u3, nx, ny, nz, flags);
+    return hipGetLastError();
+}
+
+template hipError_t launch_check_periodic_faces<double>(const double *, const double *,
+                                                        const double *, int, int, int,
+                                                        unsigned int *, hipStream_t);
+template hipError_t launch_check_periodic_faces<float>(const float *, const float *, const float *,
+                                                       int, int, int, unsigned int *, hipStream_t);
 template hipError_t launch_mass<double>(const double *, const double *, size_t, double *, int,
                                         double *, hipStream_t);
 template hipError_t launch_mass<float>(const float *, const float *, size_t, double *, int,

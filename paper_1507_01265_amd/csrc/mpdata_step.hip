@@ -14,12 +14,15 @@ namespace mpd {
 // the workgroups and grouped so that neighbouring tiles share an XCD -- and
 // advances each one time step.  With seg_ticks non-null the wall-clock
 // duration of every segment is recorded (the per-block speeds a plan tuner
-// measures while all workgroups run together).
-template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN, bool DIV>
+// measures while all workgroups run together).  TVEL: one grid whose
+// Courant numbers change in time; tv holds both time levels of the step
+// (the grid descriptor's own Courant pointers are not used).
+template <typename T, int RX, int RY, bool OPEN, bool NONOS, bool VSIGN, bool DIV, bool TVEL>
 __global__ __launch_bounds__(RX * RY) void step_kernel(const GridDesc<T> *__restrict__ grids,
                                                       const Segment *__restrict__ segs,
                                                       const int *__restrict__ wg_begin, int flip,
-                                                      double eps, long long *__restrict__ seg_ticks)
+                                                      double eps, long long *__restrict__ seg_ticks,
+                                                      TvArgs<T> tv)
 {
     __shared__ Smem<T, RX, RY, kModeStep, DIV> sm;
     smem_clear(sm);
@@ -27,18 +30,28 @@ __global__ __launch_bounds__(RX * RY) void step_kernel(const GridDesc<T> *__rest
     for (int s = b; s < e; ++s) {
         const Segment sg = segs[s];
         const long long t_start = seg_ticks ? (long long)wall_clock64() : 0;
-        const GridDesc<T> &g = grids[sg.grid];
-        if constexpr (OPEN) {
-            // open grid: interior tiles take the periodic x-y addressing
-            if (xy_interior<RX, RY>(sg.tx, sg.ty, g.nx, g.ny))
-                march<T, RX, RY, false, true, NONOS, VSIGN, DIV, kModeStep>(
-                    g, PassIO<T>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
-            else
-                march<T, RX, RY, true, true, NONOS, VSIGN, DIV, kModeStep>(
-                    g, PassIO<T>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+        auto run = [&](const GridDesc<T> &g) {
+            if constexpr (OPEN) {
+                // open grid: interior tiles take the periodic x-y addressing
+                if (xy_interior<RX, RY>(sg.tx, sg.ty, g.nx, g.ny))
+                    march<T, RX, RY, false, true, NONOS, VSIGN, DIV, kModeStep, TVEL>(
+                        g, PassIO<T>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm, tv);
+                else
+                    march<T, RX, RY, true, true, NONOS, VSIGN, DIV, kModeStep, TVEL>(
+                        g, PassIO<T>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm, tv);
+            } else {
+                march<T, RX, RY, false, false, NONOS, VSIGN, DIV, kModeStep, TVEL>(
+                    g, PassIO<T>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm, tv);
+            }
+        };
+        if constexpr (TVEL) {
+            GridDesc<T> g = grids[sg.grid];
+            g.u1 = tv.u1;
+            g.u2 = tv.u2;
+            g.u3 = tv.u3;
+            run(g);
         } else {
-            march<T, RX, RY, false, false, NONOS, VSIGN, DIV, kModeStep>(
-                g, PassIO<T>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm);
+            run(grids[sg.grid]);
         }
         __syncthreads();
         // optional per-segment duration (workgroup-uniform; one lane stores)
@@ -82,14 +95,37 @@ const TileShape *tile_shapes(int *count)
     return shapes;
 }
 
-template <typename T, int RX, int RY, bool VSIGN, bool DIV>
+template <typename T, int RX, int RY, bool VSIGN, bool DIV, bool TVEL = false>
 static const void *pick4(bool open, bool nonos)
 {
     if (open)
-        return nonos ? (const void *)step_kernel<T, RX, RY, true, true, VSIGN, DIV>
-                     : (const void *)step_kernel<T, RX, RY, true, false, VSIGN, DIV>;
-    return nonos ? (const void *)step_kernel<T, RX, RY, false, true, VSIGN, DIV>
-                 : (const void *)step_kernel<T, RX, RY, false, false, VSIGN, DIV>;
+        return nonos ? (const void *)step_kernel<T, RX, RY, true, true, VSIGN, DIV, TVEL>
+                     : (const void *)step_kernel<T, RX, RY, true, false, VSIGN, DIV, TVEL>;
+    return nonos ? (const void *)step_kernel<T, RX, RY, false, true, VSIGN, DIV, TVEL>
+                 : (const void *)step_kernel<T, RX, RY, false, false, VSIGN, DIV, TVEL>;
+}
+
+template <typename T, int RX, int RY, bool OPEN, bool DIV>
+static const void *pick_tvel(bool nonos)
+{
+    return nonos ? (const void *)step_kernel<T, RX, RY, OPEN, true, false, DIV, true>
+                 : (const void *)step_kernel<T, RX, RY, OPEN, false, false, DIV, true>;
+}
+
+// Courant numbers that change in time: built for the default launch shape
+// of each precision and boundary mode (32x24 regions; 32x32 for FP32 with
+// open boundaries), without the variable-sign option.
+template <typename T, int RX, int RY> static const void *pick_tv(bool open, bool nonos, bool div)
+{
+    if constexpr (RX == 32 && RY == 24) {
+        if (!open) return div ? pick_tvel<T, RX, RY, false, true>(nonos) : pick_tvel<T, RX, RY, false, false>(nonos);
+        if constexpr (sizeof(T) == 8)
+            return div ? pick_tvel<T, RX, RY, true, true>(nonos) : pick_tvel<T, RX, RY, true, false>(nonos);
+    }
+    if constexpr (RX == 32 && RY == 32 && sizeof(T) == 4) {
+        if (open) return div ? pick_tvel<T, RX, RY, true, true>(nonos) : pick_tvel<T, RX, RY, true, false>(nonos);
+    }
+    return nullptr;
 }
 
 // The variable-sign option and the divergent-flow term are built for the
@@ -98,6 +134,7 @@ template <typename T, int RX, int RY> static const void *pick(int variant)
 {
     const bool open = variant & kVariantOpen, nonos = variant & kVariantNonos;
     const bool vsign = variant & kVariantVsign, div = variant & kVariantDiv;
+    if (variant & kVariantTvel) return vsign ? nullptr : pick_tv<T, RX, RY>(open, nonos, div);
     if (vsign || div) {
         if constexpr (RX == 32 && (RY == 24 || RY == 32)) {
             if (vsign && div) return pick4<T, RX, RY, true, true>(open, nonos);
@@ -125,14 +162,15 @@ template <typename T> const void *step_kernel_ptr(int tile, int variant)
 template <typename T>
 hipError_t launch_persistent(const GridDesc<T> *grids, const Segment *segs, const int *wg_begin,
                              int nwg, int tile, int variant, int flip, double eps,
-                             long long *seg_ticks, hipStream_t s)
+                             long long *seg_ticks, const TvArgs<T> &tv, hipStream_t s)
 {
     int count = 0;
     const TileShape *sh = tile_shapes(&count);
     const void *k = step_kernel_ptr<T>(tile, variant);
     if (!k || nwg < 1) return hipErrorInvalidValue;
+    TvArgs<T> tva = tv;
     void *args[] = {(void *)&grids, (void *)&segs, (void *)&wg_begin, (void *)&flip, (void *)&eps,
-                    (void *)&seg_ticks};
+                    (void *)&seg_ticks, (void *)&tva};
     return hipLaunchKernel(k, dim3(nwg), dim3(sh[tile - 1].rx * sh[tile - 1].ry), args, 0, s);
 }
 
@@ -154,10 +192,10 @@ template const void *step_kernel_ptr<double>(int, int);
 template const void *step_kernel_ptr<float>(int, int);
 template hipError_t launch_persistent<double>(const GridDesc<double> *, const Segment *,
                                               const int *, int, int, int, int, double,
-                                              long long *, hipStream_t);
+                                              long long *, const TvArgs<double> &, hipStream_t);
 template hipError_t launch_persistent<float>(const GridDesc<float> *, const Segment *, const int *,
                                              int, int, int, int, double, long long *,
-                                             hipStream_t);
+                                             const TvArgs<float> &, hipStream_t);
 template const void *donor_kernel_ptr<double>(bool);
 template const void *donor_kernel_ptr<float>(bool);
 template hipError_t launch_donor<double>(const DonorArgs<double> &, bool, hipStream_t);

@@ -23,10 +23,10 @@ def _check_runtime():
 
 
 def make_params(shape, dtype=torch.float64, bc="periodic", iord=2, nonos=True, eps=1e-15, tile=0,
-                graph=True, vsign=False, div=False):
+                graph=True, vsign=False, div=False, tvel=False):
     nz, ny, nx = shape
     flags = ((0 if graph else _lib.MPDATA_FLAG_NO_GRAPH) | (_lib.MPDATA_FLAG_VSIGN if vsign else 0)
-             | (_lib.MPDATA_FLAG_DIV if div else 0))
+             | (_lib.MPDATA_FLAG_DIV if div else 0) | (_lib.MPDATA_FLAG_TVEL if tvel else 0))
     return _lib.mpdata_params(nx, ny, nz, DTYPES[dtype], BC[bc], iord, int(bool(nonos)), tile,
                               flags, 0, eps)
 
@@ -37,6 +37,7 @@ class Solver:
     vsign: fields of variable sign (|psi1| in the pseudo-velocity ratios).
     div: the divergent-flow term of the pseudo-velocity (flows that are not
     divergence-free).
+    tvel: Courant numbers that change in time (``step_tv``).
 
     psi: [nz][ny][nx] device tensor (float64 or float32), updated in place by
     ``step``; u1 [nz][ny][nx+1], u2 [nz][ny+1][nx], u3 [nz+1][ny][nx], h like
@@ -44,7 +45,7 @@ class Solver:
     """
 
     def __init__(self, psi, u1, u2, u3, h, *, bc="periodic", iord=2, nonos=True, eps=1e-15,
-                 tile=0, graph=True, stream=None, vsign=False, div=False):
+                 tile=0, graph=True, stream=None, vsign=False, div=False, tvel=False):
         if not torch.cuda.is_available():
             raise RuntimeError("libmpdata needs a GPU")
         _lib.load()
@@ -60,7 +61,7 @@ class Solver:
             if not t.is_cuda or not t.is_contiguous() or t.dtype != psi.dtype:
                 raise ValueError(f"{name}: needs a contiguous {psi.dtype} device tensor")
         self.params = make_params(psi.shape, psi.dtype, bc, iord, nonos, eps, tile, graph, vsign,
-                                  div)
+                                  div, tvel)
         self.stream = stream if stream is not None else torch.cuda.current_stream(psi.device)
         ws_bytes = _lib.mpdata_workspace_bytes(self.params)
         if ws_bytes == 0:
@@ -89,6 +90,28 @@ class Solver:
 
     def step(self, nsteps: int = 1):
         _lib.mpdata_step(self._ctx, int(nsteps))
+
+    def step_tv(self, levels):
+        """len(levels) steps with Courant numbers that change in time:
+        levels[s] = (u1, u2, u3), device tensors shaped like the solver's,
+        at the end of step s (the bound velocity is the start of step 0).
+        The last level becomes the bound velocity (kept referenced here)."""
+        if not levels:
+            return
+        for lv in levels:
+            for name, t, ref in zip(("u1", "u2", "u3"), lv, (self.u1, self.u2, self.u3)):
+                if (tuple(t.shape) != tuple(ref.shape) or t.dtype != ref.dtype or not t.is_cuda
+                        or not t.is_contiguous()):
+                    raise ValueError(f"level {name}: needs a contiguous {ref.dtype} device tensor "
+                                     f"of shape {tuple(ref.shape)}")
+        _lib.mpdata_step_tv(self._ctx, [lv[0].data_ptr() for lv in levels],
+                            [lv[1].data_ptr() for lv in levels], [lv[2].data_ptr() for lv in levels])
+        # the allocator must not hand a level's memory out before the steps
+        # that read it have run on the solver's stream
+        for lv in levels:
+            for t in lv:
+                t.record_stream(self.stream)
+        self.u1, self.u2, self.u3 = levels[-1]
 
     def mass(self) -> float:
         return _lib.mpdata_mass(self._ctx)

@@ -96,7 +96,32 @@ def test_vsign_flag_needs_a_default_launch_shape():
         assert _lib.mpdata_workspace_bytes(_params(flags=vs, tile=t)) > 0
     for t in (1, 3, 4, 6):
         assert _lib.mpdata_workspace_bytes(_params(flags=vs, tile=t)) == 0
-    assert _lib.mpdata_workspace_bytes(_params(flags=8)) == 0
+    assert _lib.mpdata_workspace_bytes(_params(flags=16)) == 0
+
+
+def test_tvel_flag_constraints():
+    """Courant numbers that change in time: iord 2, the default launch
+    shape, not with the variable-sign option (with or without DIV)."""
+    tv = _lib.MPDATA_FLAG_TVEL
+    for dtype in (0, 1):
+        for bc in (0, 1):
+            for flags in (tv, tv | _lib.MPDATA_FLAG_DIV):
+                assert _lib.mpdata_workspace_bytes(_params(flags=flags, dtype=dtype, bc=bc)) > 0
+            default = _lib.mpdata_default_tile(dtype, bc)
+            assert _lib.mpdata_workspace_bytes(_params(flags=tv, dtype=dtype, bc=bc,
+                                                       tile=default)) > 0
+            for t in range(1, _lib.mpdata_tile_count() + 1):
+                if t != default:
+                    assert _lib.mpdata_workspace_bytes(_params(flags=tv, dtype=dtype, bc=bc,
+                                                               tile=t)) == 0
+    assert _lib.mpdata_workspace_bytes(_params(flags=tv, iord=3)) == 0
+    assert _lib.mpdata_workspace_bytes(_params(flags=tv, iord=1, nonos=0)) == 0
+    assert _lib.mpdata_workspace_bytes(_params(flags=tv | _lib.MPDATA_FLAG_VSIGN)) == 0
+
+
+def test_step_tv_rejects_a_null_context():
+    lib = _lib.load()
+    assert lib.mpdata_step_tv(None, 1, None, None, None) == _lib.MPDATA_EINVAL
 
 
 def test_div_flag_needs_a_default_launch_shape():
