@@ -177,6 +177,24 @@ int mpdata_step_tv(mpdata_ctx *ctx, int32_t nsteps, const void *const *u1, const
  * NaN or Inf. */
 int mpdata_mass(mpdata_ctx *ctx, double *out);
 
+/* The mass of mpdata_mass without a context and without any allocation,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it).  M = sum of
+ * h[i]*psi[i] over n cells of the caller's device arrays psi and h (element
+ * type by dtype: MPDATA_FP64 double, MPDATA_FP32 float), reduced by the same
+ * kernels and block count as mpdata_mass (so the same bits for the same
+ * arrays), asynchronously on stream; the result, one double, is written to
+ * out_device (device memory of the caller) and may be NaN or Inf (no check:
+ * nothing is synchronised).  The partials live in a fixed 16 KiB device
+ * array of the library (one per GPU, held until the process ends), not in
+ * a workspace: calls that overlap on one GPU (other streams, other threads)
+ * share it and race; serialise them.  n from 0 to 2^31 - 1 (a grid's cell
+ * limit); MPDATA_EINVAL for a bad dtype, a NULL pointer or n outside that
+ * range, MPDATA_EDEVICE if a launch fails.  Calls no hipMalloc, hipFree or
+ * allocating routine. */
+int mpdata_mass_noalloc(int32_t dtype, const void *psi, const void *h, int64_t n,
+                        double *out_device, void *stream);
+
 /* Device-to-device copies of the state (asynchronous on the stream). */
 int mpdata_get_psi(mpdata_ctx *ctx, void *dst_device);
 int mpdata_set_psi(mpdata_ctx *ctx, const void *src_device);

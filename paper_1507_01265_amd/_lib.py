@@ -78,6 +78,8 @@ _SIGNATURES = {
                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)],
                        ctypes.c_int),
     "mpdata_mass": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "mpdata_mass_noalloc": ([ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                             ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "mpdata_get_psi": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "mpdata_set_psi": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "mpdata_sync": ([ctypes.c_void_p], ctypes.c_int),
@@ -236,6 +238,14 @@ def mpdata_mass(ctx) -> float:
     out = ctypes.c_double()
     check(load().mpdata_mass(ctx, ctypes.byref(out)), ctx)
     return out.value
+
+
+def mpdata_mass_noalloc(dtype: int, psi, h, n: int, out_device, stream):
+    """Mass of n cells of device arrays psi, h into out_device (device
+    pointers; no allocation, asynchronous on stream)."""
+    code = load().mpdata_mass_noalloc(dtype, psi, h, n, out_device, stream)
+    if code != MPDATA_OK:
+        raise MpdataError(code, "mpdata_mass_noalloc failed")
 
 
 def mpdata_get_psi(ctx, dst):

@@ -30,6 +30,7 @@ constexpr int kXcds = 8;          // XCDs of an MI355X; workgroup w runs on XCD 
 constexpr int kMinShare = 24;     // fewest planes a workgroup's share of a plan marches
 constexpr int kPipelineFill = 4;  // march iterations before a segment's first output plane
 constexpr int kMaxIord = 16;      // most passes of one step (1 donor-cell + 15 corrective)
+constexpr int64_t kMaxNoallocCells = 2147483647;  // mpdata_mass_noalloc: a grid's cell limit
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -1088,6 +1089,22 @@ int mpdata_mass(mpdata_ctx *c, double *out)
     if (!c) return MPDATA_EINVAL;
     if (!out) return fail_to(c->e.err, MPDATA_EINVAL, "out is NULL");
     return engine_mass(c->e, 0, out);
+}
+
+int mpdata_mass_noalloc(int32_t dtype, const void *psi, const void *h, int64_t n,
+                        double *out_device, void *stream)
+{
+    if (dtype != MPDATA_FP64 && dtype != MPDATA_FP32) return MPDATA_EINVAL;
+    if (!psi || !h || !out_device) return MPDATA_EINVAL;
+    if (n < 0 || n > kMaxNoallocCells) return MPDATA_EINVAL;
+    static_assert(kMassParts <= mpd::kScratchParts, "the scratch holds the partials of mpdata_mass");
+    const hipError_t r =
+        dtype == MPDATA_FP64
+            ? mpd::launch_mass_noalloc<double>((const double *)psi, (const double *)h, (size_t)n,
+                                               kMassParts, out_device, (hipStream_t)stream)
+            : mpd::launch_mass_noalloc<float>((const float *)psi, (const float *)h, (size_t)n,
+                                              kMassParts, out_device, (hipStream_t)stream);
+    return r == hipSuccess ? MPDATA_OK : MPDATA_EDEVICE;
 }
 
 int mpdata_get_psi(mpdata_ctx *c, void *dst)

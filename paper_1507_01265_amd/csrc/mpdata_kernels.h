@@ -94,6 +94,16 @@ template <typename T>
 hipError_t launch_mass(const T *psi, const T *h, size_t n, double *partials, int nparts,
                        double *result, hipStream_t s);
 
+// The mass reduction of mpdata_mass_noalloc: the same kernels as
+// launch_mass with nparts <= kScratchParts blocks, the partials and the
+// result in the library's fixed device scratch (no allocation), the result
+// copied to out (device).  Calls that overlap on one GPU share the scratch
+// and race.
+constexpr int kScratchParts = 1024;
+template <typename T>
+hipError_t launch_mass_noalloc(const T *psi, const T *h, size_t n, int nparts, double *out,
+                               hipStream_t s);
+
 // Counts (atomically, into *flags) the periodic face pairs (face n vs face
 // 0 along every axis) of u1, u2, u3 that differ bit for bit.
 template <typename T>

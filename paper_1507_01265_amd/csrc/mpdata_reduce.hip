@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "mpdata_kernels.h"
 
 namespace mpd {
@@ -221,6 +223,61 @@ hipError_t launch_validate(const T *h, const T *u1, const T *u2, const T *u3, in
     validate<T><<<blocks, 256, 0, s>>>(h, u1, u2, u3, nx, ny, nz, periodic, flags);
     return hipGetLastError();
 }
+
+// ============================================ mass without any allocation
+// The scratch of mpdata_mass_noalloc: the block partials (double-double) and
+// the result of one reduction, in a file-scope device array of fixed size
+// that every GPU the library runs on holds until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, once per device with that device current, and is
+// kept per device.
+static __device__ __align__(256) double scratch[2 * kScratchParts + 2];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(double **out)
+{
+    int dev = -1;
+    hipError_t r = hipGetDevice(&dev);
+    if (r != hipSuccess) return r;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (r != hipSuccess) return r;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_mass_noalloc(const T *psi, const T *h, size_t n, int nparts, double *out,
+                               hipStream_t s)
+{
+    if (nparts < 1 || nparts > kScratchParts) return hipErrorInvalidValue;
+    double *sp = nullptr;
+    hipError_t r = scratch_address(&sp);
+    if (r != hipSuccess) return r;
+    // every block writes its partial, so nothing needs clearing first
+    double *partials = sp, *result = sp + 2 * kScratchParts;
+    mass_partials<T><<<nparts, 256, 0, s>>>(psi, h, n, partials);
+    mass_final<<<1, 256, 0, s>>>(partials, nparts, result);
+    r = hipGetLastError();
+    if (r != hipSuccess) return r;
+    return hipMemcpyAsync(out, result, sizeof(double), hipMemcpyDeviceToDevice, s);
+}
+
+template hipError_t launch_mass_noalloc<double>(const double *, const double *, size_t, int,
+                                                double *, hipStream_t);
+template hipError_t launch_mass_noalloc<float>(const float *, const float *, size_t, int, double *,
+                                               hipStream_t);
 
 template <typename T>
 hipError_t launch_check_periodic_faces(const T *u1, const T *u2, const T *u3, int nx, int ny,
