@@ -48,6 +48,10 @@ WORKLOADS = {
     "divergent-fp64": ("divergent", "f64",
                        "rotation 512x256x64 periodic FP64 with a compressible cosine part on every "
                        "axis (divergent flow), divergent-flow term on, limiter on, iord 2"),
+    "rotation-tv-fp64": ("rotation", "f64",
+                         "rotation 512x256x64 periodic FP64 whose angular rate changes every step "
+                         "(8 cyclic time levels, rate x (1 + 0.1 sin(2 pi s/8))), the time-"
+                         "variation term on, limiter on, iord 2"),
     "batched-fp32": ("batched", "f32",
                      "96 uneven periodic grids (nx, ny log-uniform in [32, 384], nz in [16, 64]), "
                      "FP32 + FP64 limiter, constant Courant per grid, one persistent launch per "
@@ -63,19 +67,30 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(shape, word):
+def algorithmic_bytes(shape, word, tvel=False):
     """The five input arrays read once and psi written once per step:
     psi, h and psi_out are nx*ny*nz words; u1, u2, u3 carry one extra face
-    along their own axis."""
+    along their own axis.  With Courant numbers that change in time the
+    step also reads the three face arrays of its end level."""
     nz, ny, nx = shape
     n = nx * ny * nz
     faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
-    return word * (3 * n + faces)
+    return word * (3 * n + (2 if tvel else 1) * faces)
 
 
 # scheme options of a workload (iord 2, no divergent-flow term unless named here)
 OPTIONS = {"rotation-fp64-iord3": {"iord": 3}, "rotation-fp32-iord3": {"iord": 3},
-           "divergent-fp64": {"div": True}}
+           "divergent-fp64": {"div": True}, "rotation-tv-fp64": {"tvel": True}}
+
+# the cyclic time levels of rotation-tv-fp64: level s is the base rotation
+# scaled by (1 + TV_AMP sin(2 pi s / TV_LEVELS)) (a product per face, the
+# same bits on the host and the device; face n stays equal to face 0)
+TV_LEVELS, TV_AMP = 8, 0.1
+
+
+def tv_scale(s):
+    import math
+    return 1.0 + TV_AMP * math.sin(2 * math.pi * (s % TV_LEVELS) / TV_LEVELS)
 
 
 def chain_bytes(shape, word, iord, nonos=True):
@@ -145,7 +160,7 @@ def measured_traffic(workload):
     return profile_figures(workload).get("traffic_bytes_per_launch")
 
 
-def roofline(workload, shape, word, ms_per_step):
+def roofline(workload, shape, word, ms_per_step, tvel=False):
     """Roofline objects of the step kernel at the measured launch time.
 
     HBM: algorithmic bytes per launch (5 reads + 1 write per cell) over the
@@ -154,7 +169,7 @@ def roofline(workload, shape, word, ms_per_step):
     same kernel source) over the launch time against 1024 SIMDs x 2.4 GHz;
     lane instructions per output cell-step from SQ_INSTS_VALU x 64.
     `bound` names the roof closer to saturation; both are reported."""
-    abytes = algorithmic_bytes(shape, word)
+    abytes = algorithmic_bytes(shape, word, tvel)
     t = ms_per_step / 1e3
     achieved = abytes / t / 1e9
     prof = profile_figures(workload)
@@ -184,19 +199,40 @@ def make_fields(kind):
     return inputs.rotation() if kind == "rotation" else inputs.streamfunction()
 
 
+def tv_levels_device(s):
+    """The TV_LEVELS cyclic time levels of a solver's Courant numbers, built
+    on the device from the bound (level 0) arrays."""
+    base = (s.u1, s.u2, s.u3)
+    return [tuple(a * tv_scale(k) for a in base) for k in range(TV_LEVELS)]
+
+
+class _TvStepper:
+    """s.step(n) for a solver whose Courant numbers change every step: the
+    next n cyclic levels through mpdata_step_tv."""
+
+    def __init__(self, s):
+        self.s, self.levels, self.k = s, tv_levels_device(s), 0
+
+    def __call__(self, n):
+        if n:
+            self.s.step_tv([self.levels[(self.k + i + 1) % TV_LEVELS] for i in range(n)])
+            self.k = (self.k + n) % TV_LEVELS
+
+
 def time_gpu(fields, dtype_tag, steps, warmup, tile=0, iord=2, div=False, ci_target=0.0,
-             max_reps=50):
+             max_reps=50, tvel=False):
     import numpy as np
     import torch
     from paper_1507_01265_amd.solver import Solver
 
     tdt = torch.float64 if dtype_tag == "f64" else torch.float32
     f = fields if dtype_tag == "f64" else fields.astype(np.float32)
-    s = Solver.from_numpy(f, dtype=tdt, device="cuda", tile=tile, iord=iord, div=div)
+    s = Solver.from_numpy(f, dtype=tdt, device="cuda", tile=tile, iord=iord, div=div, tvel=tvel)
     stream = s.stream
+    step = _TvStepper(s) if tvel else s.step
     m0 = s.mass()
     if warmup:
-        s.step(warmup)
+        step(warmup)
     torch.cuda.synchronize()
     # the timed region is exactly `steps` steps; events between chunks of 8
     # (one replayed graph each) give per-chunk times for the spread
@@ -204,7 +240,7 @@ def time_gpu(fields, dtype_tag, steps, warmup, tile=0, iord=2, div=False, ci_tar
     events = [torch.cuda.Event(enable_timing=True) for _ in range(len(chunks) + 1)]
     events[0].record(stream)
     for c, ev in zip(chunks, events[1:]):
-        s.step(c)
+        step(c)
         ev.record(stream)
     torch.cuda.synchronize()
     ms = events[0].elapsed_time(events[-1])
@@ -218,7 +254,7 @@ def time_gpu(fields, dtype_tag, steps, warmup, tile=0, iord=2, div=False, ci_tar
     while ci_target > 0 and len(reps) < max_reps:
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        s.step(steps)
+        step(steps)
         e1.record(stream)
         torch.cuda.synchronize()
         reps.append(e0.elapsed_time(e1) / steps)
@@ -255,7 +291,7 @@ def cpu_model():
     return None
 
 
-def error_run(fields, dtype_tag, steps, iord=2, div=False):
+def error_run(fields, dtype_tag, steps, iord=2, div=False, tvel=False):
     """A fresh run of `steps` steps on the GPU from the workload's initial
     state: psi after the run (as float64) and the relative mass drift."""
     import numpy as np
@@ -263,23 +299,31 @@ def error_run(fields, dtype_tag, steps, iord=2, div=False):
     from paper_1507_01265_amd.solver import Solver
     tdt = torch.float64 if dtype_tag == "f64" else torch.float32
     f = fields if dtype_tag == "f64" else fields.astype(np.float32)
-    s = Solver.from_numpy(f, dtype=tdt, device="cuda", iord=iord, div=div)
+    s = Solver.from_numpy(f, dtype=tdt, device="cuda", iord=iord, div=div, tvel=tvel)
     m0 = s.mass()
-    s.step(steps)
+    (_TvStepper(s) if tvel else s.step)(steps)
     m1 = s.mass()
     out = s.psi.cpu().numpy().astype(np.float64)
     s.close()
     return out, (m1 - m0) / m0
 
 
-def oracle_steps(fields, steps, iord=2, div=False):
+def oracle_steps(fields, steps, iord=2, div=False, tvel=False):
     """The FP64 oracle stepped `steps` times on the host (its inputs: the
     workload's FP64 fields, or their FP32 roundings for an FP32 result);
     returns psi and the seconds it took."""
     import oracle
     f = fields
     t0 = time.perf_counter()
-    psi = oracle.run(f.psi, f.u1, f.u2, f.u3, f.h, steps, bc=f.bc, iord=iord, div=div)
+    if tvel:
+        lev = lambda k: tuple(a * tv_scale(k) for a in (f.u1, f.u2, f.u3))
+        psi, a = f.psi, lev(0)
+        for k in range(steps):
+            b = lev(k + 1)
+            psi = oracle.step_tv(psi, *a, *b, f.h, bc=f.bc, iord=iord, div=div)
+            a = b
+    else:
+        psi = oracle.run(f.psi, f.u1, f.u2, f.u3, f.h, steps, bc=f.bc, iord=iord, div=div)
     return psi, time.perf_counter() - t0
 
 
@@ -452,10 +496,12 @@ def single_grid(args, workload, fields, sub=False):
           flush=True)
     iord = OPTIONS.get(workload, {}).get("iord", 2)
     div = OPTIONS.get(workload, {}).get("div", False)
-    g = time_gpu(fields, dtag, args.steps, args.warmup, args.tile, iord, div, args.ci_target)
+    tvel = OPTIONS.get(workload, {}).get("tvel", False)
+    g = time_gpu(fields, dtag, args.steps, args.warmup, args.tile, iord, div, args.ci_target,
+                 tvel=tvel)
     ms_per_step = g["ms"] / args.steps
     value = cells * args.steps / (g["ms"] / 1e3)
-    roof, valu = roofline(workload, fields.shape, word, ms_per_step)
+    roof, valu = roofline(workload, fields.shape, word, ms_per_step, tvel)
 
     from paper_1507_01265_amd import _lib
     tile = args.tile or _lib.mpdata_default_tile(
@@ -463,7 +509,7 @@ def single_grid(args, workload, fields, sub=False):
     tx, ty, threads = _lib.mpdata_tile_info(tile)
     config = {"workload": desc, "nx": nx, "ny": ny, "nz": nz,
               "bc": "periodic" if fields.bc == 0 else "open", "iord": iord, "nonos": True,
-              "divergent_flow_term": div,
+              "divergent_flow_term": div, "time_variation_term": tvel,
               "tile": tile, "output_tile": f"{tx}x{ty}", "threads_per_workgroup": threads}
     head = {"value": value, "unit": "cell-updates/s", "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms_per_step, "dtype": dtag, "config": config} if sub else {
@@ -568,15 +614,21 @@ def main():
         return
     print(f"# generating {args.workload}", file=sys.stderr, flush=True)
     fields = make_fields(kind)
-    line = single_grid(args, args.workload, fields)
     # the default workload also times the same grid in FP32 (the metric
-    # names both precisions), with its own roofline and errors
+    # names both precisions), with its own roofline and errors; it runs
+    # first, so that the FP64 headline is not the first GPU work of the
+    # process (clocks still ramping)
+    fp32 = None
     if args.workload == "rotation-fp64" and not args.no_fp32:
-        line["fp32"] = single_grid(args, "rotation-fp32", fields, sub=True)
+        fp32 = single_grid(args, "rotation-fp32", fields, sub=True)
+    line = single_grid(args, args.workload, fields)
+    if fp32 is not None:
+        line["fp32"] = fp32
     nz, ny, nx = fields.shape
     cells = nx * ny * nz
     iord = OPTIONS.get(args.workload, {}).get("iord", 2)
     div = OPTIONS.get(args.workload, {}).get("div", False)
+    tvel = OPTIONS.get(args.workload, {}).get("tvel", False)
     if not args.no_errors:
         # errors of a fresh run of E steps against the oracle's E steps on the
         # same inputs; the FP64 oracle run is also the CPU baseline sample
@@ -589,9 +641,9 @@ def main():
             dtag = WORKLOADS[wl][1]
             print(f"# errors: {wl}, {E} steps on the GPU and in the oracle", file=sys.stderr,
                   flush=True)
-            got, drift = error_run(fields, dtag, E, iord, div)
+            got, drift = error_run(fields, dtag, E, iord, div, tvel)
             f64 = fields if dtag == "f64" else fields.astype("float32").as_f64()
-            want, el = oracle_steps(f64, E, iord, div)
+            want, el = oracle_steps(f64, E, iord, div, tvel)
             obj["errors"] = errors(got, want, drift, E)
             if obj is line and not args.no_cpu_baseline:
                 line["cpu_baseline"] = {

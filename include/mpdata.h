@@ -87,8 +87,9 @@ enum { MPDATA_BC_PERIODIC = 0, MPDATA_BC_OPEN = 1 }; /* OPEN = zero gradient */
 
 typedef struct {
     int32_t nx, ny, nz;   /* cells, each >= 1; every array < 2^31 elements
-                             and (nx+1)*(ny+1)*word < 4 GiB (one x-y plane
-                             is addressed with 32-bit byte offsets) */
+                             and (nx+1)*(ny+1)*word < 2 GiB (one x-y plane
+                             is addressed with 32-bit byte offsets, and an
+                             offset of 2^31 masks a lane) */
     int32_t dtype;        /* MPDATA_FP64 or MPDATA_FP32 */
     int32_t bc;           /* MPDATA_BC_PERIODIC or MPDATA_BC_OPEN (all axes) */
     int32_t iord;         /* 1: donor cell only; k = 2 .. 16: k - 1 corrective

@@ -2,8 +2,9 @@
 
 ``python -m paper_1507_01265_amd.build`` compiles every HIP source of the
 library.  The flags: gfx950 code only; packed FP32 instructions disabled; FMA
-contraction on (the compensated sums of the mass reduction switch it off
-locally); the step kernels are compiled without NaN semantics.
+contraction on (within expressions only in the step kernels; the
+compensated sums of the mass reduction switch it off locally); the step
+kernels are compiled without NaN semantics.
 """
 from __future__ import annotations
 
@@ -16,9 +17,15 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmpdata.so")
 # (source, extra flags): the step kernels assume finite inputs (no NaN
-# semantics, so min/max need no operand canonicalisation); the mass and
-# validation kernels keep IEEE semantics because they detect NaN/Inf.
-SOURCES = [("mpdata_step.hip", ["-fno-honor-nans"]), ("mpdata_pass.hip", ["-fno-honor-nans"]),
+# semantics, so min/max need no operand canonicalisation) and contract a
+# product and a sum into an FMA only within one expression
+# (-ffp-contract=on): the march is unrolled into several copies of one
+# iteration, and contraction across statements could round the same cell
+# differently in different copies, so that launch plans (which decide the
+# copy a plane lands in) would change bits.  The mass and validation kernels
+# keep IEEE semantics because they detect NaN/Inf.
+SOURCES = [("mpdata_step.hip", ["-fno-honor-nans", "-ffp-contract=on"]),
+           ("mpdata_pass.hip", ["-fno-honor-nans", "-ffp-contract=on"]),
            ("mpdata_reduce.hip", []), ("mpdata_abi.hip", [])]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

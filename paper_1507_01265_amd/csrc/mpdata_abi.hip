@@ -69,9 +69,10 @@ const char *check_params(const mpdata_params *p)
         (double)p->nx * p->ny * (p->nz + 1) > 2147483647.0)
         return "face arrays too large (> 2^31 elements)";
     if (p->dtype != MPDATA_FP64 && p->dtype != MPDATA_FP32) return "dtype must be FP64 or FP32";
-    // the step kernel addresses one x-y plane of an array with 32-bit byte offsets
-    if ((double)(p->nx + 1) * (p->ny + 1) * (p->dtype == MPDATA_FP64 ? 8 : 4) >= 4294967296.0)
-        return "x-y plane too large (>= 4 GiB)";
+    // the step kernel addresses one x-y plane of an array with 32-bit byte
+    // offsets and masks lanes with an offset of 2^31, past every plane
+    if ((double)(p->nx + 1) * (p->ny + 1) * (p->dtype == MPDATA_FP64 ? 8 : 4) >= 2147483648.0)
+        return "x-y plane too large (>= 2 GiB)";
     if (p->bc != MPDATA_BC_PERIODIC && p->bc != MPDATA_BC_OPEN) return "bc must be PERIODIC or OPEN";
     if (p->iord < 1 || p->iord > kMaxIord) return "iord must be 1 .. 16";
     if (p->nonos != 0 && p->nonos != 1) return "nonos must be 0 or 1";

@@ -214,7 +214,7 @@ __device__ __forceinline__ T limited(T v, F bup_a, F bdn_a, F bup_b, F bdn_b)
 // the plane's bytes, built in scalar registers) and a loop-invariant 32-bit
 // byte offset per lane.  No 64-bit address arithmetic per access, and an
 // offset past the plane reads zero instead of leaving the array.  The host
-// keeps every plane below 4 GiB.
+// keeps every plane below 2 GiB.
 using Rsrc = __amdgpu_buffer_rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
 
@@ -225,6 +225,7 @@ template <typename T> __device__ __forceinline__ Rsrc plane_rsrc(const T *base, 
 }
 
 // byte_off: per-lane offset; s_off: workgroup-uniform offset added to it
+// (their sum stays below 2^32; an offset past the plane reads zero)
 template <typename T> __device__ __forceinline__ T bload(Rsrc r, unsigned byte_off, unsigned s_off = 0)
 {
     if constexpr (sizeof(T) == 8)
@@ -240,6 +241,25 @@ template <typename T> __device__ __forceinline__ void bstore(Rsrc r, unsigned by
                                               r, (int)byte_off, 0, 0);
     else
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
+}
+
+// A byte offset that every plane's range check rejects: the host keeps each
+// plane below 2 GiB, so 2^31 lies past its end (and 2^31 plus an access
+// size does not wrap).  A read there returns zero, a write is dropped.
+constexpr unsigned kOobOffset = 0x80000000u;
+
+// Store into plane `plane` of an array (when the workgroup-uniform plane_ok
+// holds; plane 0 otherwise) for the lanes where lane_ok.  Every lane issues
+// it, a disabled lane at kOobOffset, so that no branch makes the number of
+// memory operations a wave has in flight depend on its lanes: the counter
+// waits the compiler places before the use of a prefetched value then stop
+// at that value's load, not at the prefetches issued after it.
+template <typename T>
+__device__ __forceinline__ void bstore_if(T *base, int plane, bool plane_ok, unsigned plane_elems,
+                                          unsigned byte_off, bool lane_ok, T v)
+{
+    bstore<T>(plane_rsrc<T>(base, plane_ok ? plane : 0, plane_elems),
+              plane_ok && lane_ok ? byte_off : kOobOffset, v);
 }
 
 // Lane exchange along x inside a wave.  A workgroup's rows are RX lanes long
@@ -409,7 +429,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         p_ring = (side ? RY + 1 : 0) * PX + col + 1;
     }
     const unsigned o_ring = cell_of<OPXY>(rgy, ny) * nx + cell_of<OPXY>(rgx, nx);
-    // byte offsets within a plane (the host keeps every plane below 4 GiB)
+    // byte offsets within a plane (the host keeps every plane below 2 GiB)
     const unsigned b_c = o_c * (unsigned)sizeof(T);
     const unsigned b_u1lo = o_u1lo * (unsigned)sizeof(T), b_u1hi = o_u1hi * (unsigned)sizeof(T);
     const unsigned b_u2lo = o_u2lo * (unsigned)sizeof(T), b_u2hi = o_u2hi * (unsigned)sizeof(T);
@@ -477,8 +497,11 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     };
     // The ring threads load their ring cell of a plane late in the
     // iteration before it is stored (it is not held across the heavy phase).
+    // Issued by every lane (the others read at kOobOffset and get zero), so
+    // that it leaves no branch around a memory operation (see bstore_if).
     auto load_ring = [&](int k) {
-        return has_ring ? bload<T>(plane_rsrc(psi_in, k, pc_cells), b_ring) : T(0);
+        if constexpr (kPass) return T(0);
+        else return bload<T>(plane_rsrc(psi_in, k, pc_cells), has_ring ? b_ring : kOobOffset);
     };
 
     const int t0 = z0 - 2, tend = z1 + 2;
@@ -528,6 +551,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     // t-1 and t-2 before (D) (below): measured faster there, slower with
     // 32x24 regions and on periodic grids
     constexpr bool kEarlyS3 = !kDpp && OPZ && RY == 32;
+    constexpr bool kFenceFaces = kDpp || OPXY || OPZ;
     T r_p1_m1 = T(0), r_p1_m2 = T(0), r_p1_m3 = T(0);
     T r_c1_m1 = T(0), r_c2_m1 = T(0), r_c3_m1 = T(0), r_h_m1 = T(0);
     T r_d_m1 = T(0);  // divergence of the column's cell at plane t-1 (DIV)
@@ -568,8 +592,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             const T fc2hi = sFC2[q + YP];
             const T fc2lo = fc2_m3;
             const T res = p1_m3 - (((fc1hi - fc1_m3) + (fc2hi - fc2lo)) + (fc3_m2 - fc3_m3)) * rh_m3;
-            if (is_out && t >= z0 + 3 && t <= tend)
-                bstore<T>(plane_rsrc<T>(psi_out, t - 3, pc_cells), b_c, res);
+            bstore_if<T>(psi_out, t - 3, t >= z0 + 3 && t <= tend, pc_cells, b_c, is_out, res);
         }
 
         const bool own_plane = t >= z0 && t < z1;  // plane t is one of the segment's
@@ -584,9 +607,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                          zlo ? M_c : fmax(M_c, M_m1));
             zmn_c = fmin(fmin(fmin(sPm[q + cxm], sPm[q + cxp]), fmin(sPm[q + cym], sPm[q + cyp])),
                          zlo ? m_c : fmin(m_c, m_m1));
-            if (MODE == kModeMid && NONOS && is_out && own_plane) {
-                bstore<T>(plane_rsrc<T>(io.mx, t, pc_cells), b_c, M_c);
-                bstore<T>(plane_rsrc<T>(io.mn, t, pc_cells), b_c, m_c);
+            if constexpr (MODE == kModeMid && NONOS) {
+                bstore_if<T>(io.mx, t, own_plane, pc_cells, b_c, is_out, M_c);
+                bstore_if<T>(io.mn, t, own_plane, pc_cells, b_c, is_out, m_c);
             }
         } else {
             // ---- S1+S2 at plane t
@@ -601,9 +624,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             const bool zlo = OZ && t <= 0;
             zmx_c = fmax(fmax(fmax(pL, pR), fmax(pD, pU)), zlo ? cur.pn : fmax(cur.pn, pn_m1));
             zmn_c = fmin(fmin(fmin(pL, pR), fmin(pD, pU)), zlo ? cur.pn : fmin(cur.pn, pn_m1));
-            if (MODE == kModeHead && NONOS && is_out && own_plane) {
+            if constexpr (MODE == kModeHead && NONOS) {
                 // psi1 for the next pass's bounds (psi^n stays in the input)
-                bstore<T>(plane_rsrc<T>(io.mx, t, pc_cells), b_c, p1_c);
+                bstore_if<T>(io.mx, t, own_plane, pc_cells, b_c, is_out, p1_c);
             }
         }
         sQ[s0][q] = p1_c;  // psi1(t-3) of this slot was last read before (B)
@@ -715,8 +738,11 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                 if (zero_v1) v1 = T(0);
             }
             // the three faces are scheduled one after another: each face's
-            // temporaries die before the next face's reads are issued
-            __builtin_amdgcn_sched_barrier(0);
+            // temporaries die before the next face's reads are issued (FP64,
+            // at its register limit, and open FP32 grids); periodic FP32 lets
+            // the compiler hoist the y-face's LDS reads (3.5 % faster step,
+            // measured)
+            if constexpr (kFenceFaces) __builtin_amdgcn_sched_barrier(0);
             {
                 // y-face between a = (ly-1) and b = own; transverse axes z then x
                 T d_ya = T(0);
@@ -746,7 +772,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                 if constexpr (TVEL) v2 = v2 + T(0.5) * (w2_m1 - u2_m1);
                 if (zero_v2) v2 = T(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (kFenceFaces) __builtin_amdgcn_sched_barrier(0);
             if constexpr (!kDpp) {
                 q6_y = sQ[s2][q + YM];
                 if (NONOS) {
@@ -846,12 +872,11 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                 // the limited velocity of the segment's planes and of its
                 // z-faces (face nz from the segment that ends there)
                 const int r = t - 2, f = t - 1;
-                if (r >= z0 && r < z1) {
-                    if (w1_lane) bstore<T>(plane_rsrc<T>(io.w1, r, pc_u1), b_w1, vt1);
-                    if (w2_lane) bstore<T>(plane_rsrc<T>(io.w2, r, pc_u2), b_w2, vt2);
-                }
-                if (is_out && ((f >= z0 && f < z1) || (f == nz && z1 == nz)))
-                    bstore<T>(plane_rsrc<T>(io.w3, f, pc_cells), b_c, vt3);
+                const bool r_ok = r >= z0 && r < z1;
+                bstore_if<T>(io.w1, r, r_ok, pc_u1, b_w1, w1_lane, vt1);
+                bstore_if<T>(io.w2, r, r_ok, pc_u2, b_w2, w2_lane, vt2);
+                bstore_if<T>(io.w3, f, (f >= z0 && f < z1) || (f == nz && z1 == nz), pc_cells, b_c,
+                             is_out, vt3);
             }
             if constexpr (!kDpp) p2_xm = q6_x;
             fc1_r = donor(p2_xm, p1_m2, vt1);

@@ -157,10 +157,11 @@ def test_more_corrective_passes_need_chain_buffers():
 
 
 def test_plane_limit_depends_on_word_size():
-    # one x-y plane is addressed with 32-bit byte offsets: 30001^2 words fit
-    # in 4 GiB as FP32, not as FP64
-    assert _lib.mpdata_workspace_bytes(_params(nx=30000, ny=30000, nz=1, dtype=1)) > 0
-    assert _lib.mpdata_workspace_bytes(_params(nx=30000, ny=30000, nz=1, dtype=0)) == 0
+    # one x-y plane is addressed with 32-bit byte offsets below 2^31 (an
+    # offset of 2^31 masks a lane): 20001^2 words fit in 2 GiB as FP32, not
+    # as FP64
+    assert _lib.mpdata_workspace_bytes(_params(nx=20000, ny=20000, nz=1, dtype=1)) > 0
+    assert _lib.mpdata_workspace_bytes(_params(nx=20000, ny=20000, nz=1, dtype=0)) == 0
 
 
 def test_null_and_misaligned_pointers_are_rejected():

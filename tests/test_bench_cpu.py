@@ -28,6 +28,22 @@ def test_algorithmic_bytes_are_five_reads_and_one_write():
     assert abs(want / (nx * ny * nz) - 48.2) < 0.05
 
 
+def test_time_levels_add_three_face_arrays_and_keep_periodic_faces():
+    import numpy as np
+    shape = (16, 8, 4)
+    nz, ny, nx = shape
+    faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+    assert (bench.algorithmic_bytes(shape, 8, tvel=True) - bench.algorithmic_bytes(shape, 8)
+            == 8 * faces)
+    assert bench.tv_scale(0) == 1.0 and bench.tv_scale(bench.TV_LEVELS) == 1.0
+    assert len({bench.tv_scale(k) for k in range(bench.TV_LEVELS)}) > 2
+    u = np.random.default_rng(0).uniform(-0.4, 0.4, (3, 4, 9))
+    u[..., -1] = u[..., 0]
+    for k in range(bench.TV_LEVELS):
+        v = u * bench.tv_scale(k)
+        assert np.array_equal(v[..., -1], v[..., 0])
+
+
 def test_chain_bytes_by_design():
     """iord 3 = head (5 in, psi out, 3 velocity faces, psi1) + last
     (iterate, h, psi1, psi^n and 3 velocity faces in, psi out)."""
