@@ -36,8 +36,8 @@
  *    bit (rounding is monotone).  Mass sums are compensated (double-double).
  *  - Range of psi: FP64 steps stay finite for |psi| below about 1e100 (the
  *    pseudo-velocity divides once per face by a product of three ratio
- *    denominators); FP32 steps scale that product exactly by powers of two
- *    and stay finite for |psi| below about 1e37, at any small magnitude.
+ *    denominators); FP32 steps take the three ratios separately and stay
+ *    finite for |psi| below about 1e37, at any small magnitude.
  *  - Pointers named "device" are device memory of the current HIP device;
  *    the caller owns them and keeps them alive until mpdata_destroy().  The
  *    library allocates no device memory: everything it needs beyond the
