@@ -220,7 +220,7 @@ class _TvStepper:
 
 
 def time_gpu(fields, dtype_tag, steps, warmup, tile=0, iord=2, div=False, ci_target=0.0,
-             max_reps=50, tvel=False):
+             max_reps=50, tvel=False, before_warmup=None):
     import numpy as np
     import torch
     from paper_1507_01265_amd.solver import Solver
@@ -231,6 +231,11 @@ def time_gpu(fields, dtype_tag, steps, warmup, tile=0, iord=2, div=False, ci_tar
     stream = s.stream
     step = _TvStepper(s) if tvel else s.step
     m0 = s.mass()
+    if before_warmup is not None:
+        # other GPU work, run between this solver's set-up (host work, the
+        # GPU idle) and its warm-up, so that the timed steps do not start
+        # while the clocks still ramp up from idle
+        before_warmup()
     if warmup:
         step(warmup)
     torch.cuda.synchronize()
@@ -293,7 +298,9 @@ def cpu_model():
 
 def error_run(fields, dtype_tag, steps, iord=2, div=False, tvel=False):
     """A fresh run of `steps` steps on the GPU from the workload's initial
-    state: psi after the run (as float64) and the relative mass drift."""
+    state: psi after the run (the device tensor; the caller copies it to the
+    host later, so that the GPU is not left idle meanwhile) and the relative
+    mass drift."""
     import numpy as np
     import torch
     from paper_1507_01265_amd.solver import Solver
@@ -303,7 +310,7 @@ def error_run(fields, dtype_tag, steps, iord=2, div=False, tvel=False):
     m0 = s.mass()
     (_TvStepper(s) if tvel else s.step)(steps)
     m1 = s.mass()
-    out = s.psi.cpu().numpy().astype(np.float64)
+    out = s.psi
     s.close()
     return out, (m1 - m0) / m0
 
@@ -482,10 +489,10 @@ RUN_STEPS = {"rotation": 100, "divergent": 100, "streamfunction": 50}
 
 
 def error_steps(args, kind):
-    return args.error_steps or min(args.steps, RUN_STEPS.get(kind, args.steps))
+    return args.error_steps or RUN_STEPS.get(kind, args.steps)
 
 
-def single_grid(args, workload, fields, sub=False):
+def single_grid(args, workload, fields, sub=False, before_warmup=None):
     """Times exactly --steps steps after --warmup on one grid; returns the
     JSON object of the result (the bench line's fields, or a sub-object)."""
     kind, dtag, desc = WORKLOADS[workload]
@@ -498,7 +505,7 @@ def single_grid(args, workload, fields, sub=False):
     div = OPTIONS.get(workload, {}).get("div", False)
     tvel = OPTIONS.get(workload, {}).get("tvel", False)
     g = time_gpu(fields, dtag, args.steps, args.warmup, args.tile, iord, div, args.ci_target,
-                 tvel=tvel)
+                 tvel=tvel, before_warmup=before_warmup)
     ms_per_step = g["ms"] / args.steps
     value = cells * args.steps / (g["ms"] / 1e3)
     roof, valu = roofline(workload, fields.shape, word, ms_per_step, tvel)
@@ -556,9 +563,11 @@ def main():
                     help="skip the error check against the oracle (and with it the CPU baseline)")
     ap.add_argument("--no-fp32", action="store_true",
                     help="rotation-fp64: do not also time the FP32 grid")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="rotation-fp64: do not also time the 96-grid batched workload")
     ap.add_argument("--error-steps", type=int, default=0,
-                    help="steps of the error check (0 = min(--steps, the workload's configured "
-                         "run: 100 rotation, 50 streamfunction))")
+                    help="steps of the error check (0 = the workload's configured run: 100 "
+                         "rotation, 50 streamfunction)")
     ap.add_argument("--ci-target", type=float, default=0.01,
                     help="after the timed steps, repeat them until the 95%% Student-t half-width "
                          "is within this fraction of the mean (at most 50 times; 0 = off)")
@@ -614,44 +623,72 @@ def main():
         return
     print(f"# generating {args.workload}", file=sys.stderr, flush=True)
     fields = make_fields(kind)
-    # the default workload also times the same grid in FP32 (the metric
-    # names both precisions), with its own roofline and errors; it runs
-    # first, so that the FP64 headline is not the first GPU work of the
-    # process (clocks still ramping)
-    fp32 = None
-    if args.workload == "rotation-fp64" and not args.no_fp32:
-        fp32 = single_grid(args, "rotation-fp32", fields, sub=True)
-    line = single_grid(args, args.workload, fields)
-    if fp32 is not None:
-        line["fp32"] = fp32
     nz, ny, nx = fields.shape
     cells = nx * ny * nz
     iord = OPTIONS.get(args.workload, {}).get("iord", 2)
     div = OPTIONS.get(args.workload, {}).get("div", False)
     tvel = OPTIONS.get(args.workload, {}).get("tvel", False)
+    # the default workload also times the same grid in FP32 (the metric names
+    # both precisions) and the batched workload (96 uneven FP32 grids, one
+    # persistent launch per step, against the same grids run one after
+    # another through the single-grid path)
+    precisions = [args.workload] + (["rotation-fp32"] if args.workload == "rotation-fp64"
+                                    and not args.no_fp32 else [])
+    # errors of a fresh run of E steps (the workload's configured run)
+    # against the oracle's E steps on the same inputs; the FP64 oracle run is
+    # also the CPU baseline sample.  The oracle runs first, on the host.
+    E = error_steps(args, kind)
+    want = {}
     if not args.no_errors:
-        # errors of a fresh run of E steps against the oracle's E steps on the
-        # same inputs; the FP64 oracle run is also the CPU baseline sample
         import oracle
         if args.cpu_threads:
             oracle.set_threads(args.cpu_threads)
-        E = error_steps(args, kind)
-        subs = [(line, args.workload)] + ([(line["fp32"], "rotation-fp32")] if "fp32" in line else [])
-        for obj, wl in subs:
+        for wl in precisions:
             dtag = WORKLOADS[wl][1]
-            print(f"# errors: {wl}, {E} steps on the GPU and in the oracle", file=sys.stderr,
-                  flush=True)
-            got, drift = error_run(fields, dtag, E, iord, div, tvel)
+            print(f"# oracle: {wl}, {E} steps", file=sys.stderr, flush=True)
             f64 = fields if dtag == "f64" else fields.astype("float32").as_f64()
-            want, el = oracle_steps(f64, E, iord, div, tvel)
-            obj["errors"] = errors(got, want, drift, E)
-            if obj is line and not args.no_cpu_baseline:
-                line["cpu_baseline"] = {
-                    "value": cells * E / el, "unit": "cell-updates/s", "cores": oracle.threads(),
-                    "kind": "oracle",
-                    "sample": f"{nx}x{ny}x{nz} {args.workload} inputs, {E} FP64 steps of the "
-                              f"whole grid (the run the errors are taken against), {el:.1f} s",
-                    "cpu_model": cpu_model()}
+            want[wl] = oracle_steps(f64, E, iord, div, tvel)
+    # Everything else runs on the GPU after the headline grid is set up and
+    # before its warm-up: the FP32 grid (its error run before its own
+    # warm-up), the batched workload and last the GPU run the headline's
+    # errors are taken from.  A new run needs about 100 steps (20 ms) of the
+    # same kernel before its step time settles (measured in FP64: the first
+    # 100 steps after a set-up or an idle GPU take 182-197 us, later ones
+    # 167 us, whatever ran before), so an error run of the configured length
+    # right before the warm-up leaves the timed steps in steady state.
+    extra, got = {}, {}
+
+    def error_gpu(wl):
+        if not args.no_errors:
+            print(f"# errors: {wl}, {E} steps on the GPU", file=sys.stderr, flush=True)
+            got[wl] = error_run(fields, WORKLOADS[wl][1], E, iord, div, tvel)
+
+    def others():
+        if "rotation-fp32" in precisions:
+            extra["fp32"] = single_grid(args, "rotation-fp32", fields, sub=True,
+                                        before_warmup=lambda: error_gpu("rotation-fp32"))
+        if args.workload == "rotation-fp64" and not args.no_batched:
+            r = bench_batched(args)
+            extra["batched"] = {
+                "value": r["cells"] * r["steps"] / (r["ms"] / 1e3), "unit": "cell-updates/s",
+                "steps": r["steps"], "warmup": args.warmup, "ms_per_step": r["ms"] / r["steps"],
+                "dtype": "f32",
+                "config": {"workload": WORKLOADS["batched-fp32"][2], "cells": r["cells"]},
+                **{k: v for k, v in r["extra"].items() if k != "tuner_log"}}
+        error_gpu(args.workload)
+    line = single_grid(args, args.workload, fields, before_warmup=others)
+    line.update(extra)
+    for wl in precisions if not args.no_errors else []:
+        obj = line if wl == args.workload else line["fp32"]
+        (g, drift), (w, el) = got[wl], want[wl]
+        obj["errors"] = errors(g.cpu().numpy().astype("float64"), w, drift, E)
+        if obj is line and not args.no_cpu_baseline:
+            line["cpu_baseline"] = {
+                "value": cells * E / el, "unit": "cell-updates/s", "cores": oracle.threads(),
+                "kind": "oracle",
+                "sample": f"{nx}x{ny}x{nz} {args.workload} inputs, {E} FP64 steps of the "
+                          f"whole grid (the run the errors are taken against), {el:.1f} s",
+                "cpu_model": cpu_model()}
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

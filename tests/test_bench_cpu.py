@@ -133,7 +133,7 @@ def test_error_metrics():
 def test_error_steps_follow_the_configured_run():
     import argparse
     a = argparse.Namespace(error_steps=0, steps=20)
-    assert bench.error_steps(a, "rotation") == 20
+    assert bench.error_steps(a, "rotation") == 100  # the configured run, whatever --steps
     a.steps = 300
     assert bench.error_steps(a, "rotation") == 100
     assert bench.error_steps(a, "streamfunction") == 50
