@@ -102,7 +102,8 @@ typedef struct {
                              single-grid contexts only */
     int32_t nonos;        /* 1: non-oscillatory limiter on (needs iord >= 2) */
     int32_t tile;         /* launch shape: 0 = library default, else an id
-                             from mpdata_tile_count()/mpdata_tile_info() */
+                             from mpdata_tile_count()/mpdata_tile_info();
+                             tile 7 (24x32 regions) is built for FP32 only */
     int32_t flags;        /* MPDATA_FLAG_* bits, 0 = defaults */
     int32_t reserved;     /* must be 0 */
     double eps;           /* >= 1e-30 and finite (MPDATA_EINVAL otherwise),
@@ -245,8 +246,15 @@ typedef struct {
     int32_t tile;            /* launch shape id, 1..mpdata_tile_count() */
     int32_t nwg;             /* workgroups of the persistent launch, >= 1 */
     int32_t nseg;            /* number of segments */
-    int32_t reserved;        /* must be 0 */
-    const int32_t *seg;      /* host, nseg x 5 int32: grid, tile_x, tile_y, z0, z1 */
+    int32_t seg_cols;        /* 0 or 5: seg rows are grid, tile_x, tile_y, z0, z1
+                                (every grid in shape `tile`); 6: a sixth column
+                                names the segment's shape, so that each grid
+                                takes its own (per-size-class shapes in one
+                                launch): tile 5 or 7 (32x24 and 24x32 regions,
+                                768 threads each), the same for all segments of
+                                a grid, FP32 periodic grids without VSIGN, DIV
+                                or TVEL; `tile` is then 5 or 7 as well */
+    const int32_t *seg;      /* host, nseg x seg_cols int32 */
     const int32_t *wg_begin; /* host, nwg + 1 int32: workgroup w runs segments
                                 [wg_begin[w], wg_begin[w+1]) in order */
 } mpdata_plan;

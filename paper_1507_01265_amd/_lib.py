@@ -42,7 +42,7 @@ class mpdata_params(ctypes.Structure):
 
 class mpdata_plan(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("nwg", ctypes.c_int32), ("nseg", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("seg", ctypes.POINTER(ctypes.c_int32)),
+                ("seg_cols", ctypes.c_int32), ("seg", ctypes.POINTER(ctypes.c_int32)),
                 ("wg_begin", ctypes.POINTER(ctypes.c_int32))]
 
 
@@ -208,6 +208,12 @@ def mpdata_tile_info(tile_id: int):
     return tx.value, ty.value, th.value
 
 
+def mpdata_tile_built(dtype: int, tile: int) -> bool:
+    """Whether launch shape `tile` is built for `dtype` (the parameter check
+    of a small grid with that shape passes)."""
+    return mpdata_workspace_bytes(mpdata_params(8, 8, 4, dtype, 0, 2, 1, tile, 0, 0, 1e-15)) > 0
+
+
 def mpdata_workspace_bytes(params: mpdata_params) -> int:
     return int(load().mpdata_workspace_bytes(ctypes.byref(params)))
 
@@ -299,12 +305,14 @@ def mpdata_batch_default_plan_size(params, tile: int = 0):
 
 
 def make_plan(tile: int, seg, wg_begin):
-    """mpdata_plan over host int32 arrays (seg: nseg x 5, wg_begin: nwg + 1);
-    returns (plan, keepalive)."""
+    """mpdata_plan over host int32 arrays (seg: nseg x 5, or nseg x 6 with a
+    per-segment shape id; wg_begin: nwg + 1); returns (plan, keepalive)."""
     import numpy as np
-    seg = np.ascontiguousarray(seg, dtype=np.int32).reshape(-1, 5)
+    seg = np.ascontiguousarray(seg, dtype=np.int32)
+    cols = seg.shape[1] if seg.ndim == 2 else 5
+    seg = seg.reshape(-1, cols)
     wg_begin = np.ascontiguousarray(wg_begin, dtype=np.int32)
-    plan = mpdata_plan(tile, len(wg_begin) - 1, len(seg), 0,
+    plan = mpdata_plan(tile, len(wg_begin) - 1, len(seg), cols,
                        seg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                        wg_begin.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return plan, (seg, wg_begin)

@@ -3,7 +3,10 @@
 Two decisions are made from measurements on the GPU:
 
 * the launch shape (x-y region of a workgroup; its output tile is the region
-  minus a 2-cell halo): every candidate shape is timed on the batch;
+  minus a 2-cell halo): every candidate shape is timed on the batch, and
+  for FP32 periodic batches a mixed plan gives each grid the one of the two
+  768-thread regions (32x24, 24x32) whose tiles cost it less in the measured
+  runs -- per-size-class shapes in one persistent launch;
 * the assignment of (grid, tile) blocks to the workgroups of the persistent
   kernel: blocks are placed by longest-processing-time-first (LPT) greedy
   scheduling onto the workgroup with the least accumulated cost.  The costs
@@ -73,7 +76,7 @@ def plan_from_owner(segs, owner, nwg):
 
 @dataclasses.dataclass
 class Tuned:
-    tile: int
+    tile: object           # a tile id, or "mixed" (per-grid shapes, plan[0] = 5)
     plan: tuple            # (tile, seg, wg_begin) for Batch(plan=...)
     ms_per_step: float
     makespan_static: float
@@ -90,6 +93,21 @@ def time_steps(batch, steps):
     b.record(batch.stream)
     torch.cuda.synchronize()
     return a.elapsed_time(b) / steps
+
+
+MIXED_TILES = (5, 7)  # the 768-thread regions one mixed launch combines
+
+
+def mixed_segments(shapes, choice):
+    """Whole-tile segments with a sixth column, the shape of each grid
+    (choice[g] in MIXED_TILES)."""
+    rows = []
+    for g, (shp, tile) in enumerate(zip(shapes, choice)):
+        ntx, nty = tiles_of(shp, tile)
+        for ty in range(nty):
+            for tx in range(ntx):
+                rows.append((g, tx, ty, 0, shp[0], tile))
+    return np.array(rows, dtype=np.int32).reshape(-1, 6)
 
 
 def option_tiles():
@@ -111,12 +129,14 @@ def tune(grids, *, bc="periodic", nonos=True, eps=1e-15, tiles=None, steps=4, pr
     dt = _lib.MPDATA_FP32 if dtype == torch.float32 else _lib.MPDATA_FP64
     if tiles is None:
         tiles = (option_tiles() if (vsign or div)
-                 else list(range(1, _lib.mpdata_tile_count() + 1)))
+                 else [t for t in range(1, _lib.mpdata_tile_count() + 1)
+                       if _lib.mpdata_tile_built(dt, t)])
     opts = dict(bc=bc, nonos=nonos, eps=eps, vsign=vsign, div=div)
     shapes = [tuple(g[0].shape) for g in grids]
     saved = [g[0].clone() for g in grids]
     log = []
     best = None
+    per_tile = {}  # tile -> (segments, measured ticks per segment, nwg)
     for tile in tiles:
         per, cus = _lib.mpdata_occupancy(dt, tile, _lib.MPDATA_BC_OPEN if bc == "open" else 0,
                                          int(bool(nonos)))
@@ -136,6 +156,7 @@ def tune(grids, *, bc="periodic", nonos=True, eps=1e-15, tiles=None, steps=4, pr
         measured = np.empty(len(segs))
         for r, t in zip(seg_sorted.tolist(), ticks):
             measured[key[tuple(r)]] = t
+        per_tile[tile] = (segs, measured, nwg)
         owner1, loads1 = lpt(measured, nwg)
         plan1 = (tile, *plan_from_owner(segs, owner1, nwg))
         b = Batch(grids, plan=plan1, **opts)
@@ -152,6 +173,34 @@ def tune(grids, *, bc="periodic", nonos=True, eps=1e-15, tiles=None, steps=4, pr
         for ms, plan, mk in ((ms0, plan0, loads0.max()), (ms1, plan1, loads1.max())):
             if best is None or ms < best.ms_per_step:
                 best = Tuned(tile, plan, ms, float(loads0.max()), float(loads1.max()), log)
+    if (dtype == torch.float32 and bc == "periodic" and not vsign and not div
+            and all(t in per_tile for t in MIXED_TILES)):
+        # per-grid shapes: each grid takes the region whose tiles cost it
+        # less, by the per-segment times measured with all workgroups busy
+        cost = {}
+        for t in MIXED_TILES:
+            segs_t, meas_t, _ = per_tile[t]
+            cost[t] = np.bincount(segs_t[:, 0], weights=meas_t, minlength=len(grids))
+        choice = [min(MIXED_TILES, key=lambda t: cost[t][g]) for g in range(len(grids))]
+        segs_m = mixed_segments(shapes, choice)
+        key = {t: {tuple(r): m for r, m in zip(per_tile[t][0].tolist(), per_tile[t][1])}
+               for t in MIXED_TILES}
+        meas_m = np.array([key[r[5]][tuple(r[:5])] for r in segs_m.tolist()])
+        nwg = per_tile[MIXED_TILES[0]][2]
+        owner_m, loads_m = lpt(meas_m, nwg)
+        plan_m = (MIXED_TILES[0], *plan_from_owner(segs_m, owner_m, nwg))
+        b = Batch(grids, plan=plan_m, **opts)
+        b.step(2)
+        ms_m = time_steps(b, steps)
+        b.close()
+        entry = dict(tile="mixed", shapes={str(t): choice.count(t) for t in MIXED_TILES},
+                     nwg=nwg, nseg=len(segs_m), ms_measured=ms_m,
+                     makespan_measured_ticks=float(loads_m.max()))
+        log.append(entry)
+        if verbose:
+            print("tune", entry, flush=True)
+        if ms_m < best.ms_per_step:
+            best = Tuned("mixed", plan_m, ms_m, float("nan"), float(loads_m.max()), log)
     for g, s in zip(grids, saved):
         g[0].copy_(s)
     torch.cuda.synchronize()

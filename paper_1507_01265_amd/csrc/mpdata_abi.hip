@@ -87,6 +87,9 @@ const char *check_params(const mpdata_params *p)
     int count = 0;
     mpd::tile_shapes(&count);
     if (p->tile < 0 || p->tile > count) return "tile id out of range";
+    if (p->tile == 7 && p->dtype != MPDATA_FP32)
+        return "tile 7 (24x32 regions) is built for FP32 only (FP64 exchanges x-neighbours "
+               "between the lanes of a wave, which needs rows that tile a wave)";
     if (p->iord > 2 && p->tile != 0 && p->tile != default_tile(p->dtype, p->bc))
         return "iord > 2 runs on the default launch shape (tile 0)";
     if ((p->flags & (MPDATA_FLAG_VSIGN | MPDATA_FLAG_DIV)) && p->tile != 0 &&
@@ -244,7 +247,9 @@ void default_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
 
 // A plan must cover every output tile of every grid over all its planes
 // exactly once.
-const char *check_plan(const std::vector<mpdata_params> &grids, int tile,
+// grid_tile: the launch shape of each grid (its segments' tiles are counted
+// in that shape's tiling)
+const char *check_plan(const std::vector<mpdata_params> &grids, const std::vector<int> &grid_tile,
                        const std::vector<mpd::Segment> &segs, const std::vector<int> &wg_begin)
 {
     const int nwg = (int)wg_begin.size() - 1;
@@ -253,11 +258,13 @@ const char *check_plan(const std::vector<mpdata_params> &grids, int tile,
         if (wg_begin[w + 1] < wg_begin[w]) return "wg_begin must be non-decreasing";
     std::vector<size_t> base(grids.size() + 1, 0);
     for (size_t g = 0; g < grids.size(); ++g)
-        base[g + 1] = base[g] + (size_t)tiles_x(grids[g], tile) * tiles_y(grids[g], tile) * grids[g].nz;
+        base[g + 1] = base[g] + (size_t)tiles_x(grids[g], grid_tile[g]) *
+                                    tiles_y(grids[g], grid_tile[g]) * grids[g].nz;
     std::vector<unsigned char> seen(base.back(), 0);
     for (const mpd::Segment &s : segs) {
         if (s.grid < 0 || s.grid >= (int)grids.size()) return "segment grid out of range";
         const mpdata_params &p = grids[s.grid];
+        const int tile = grid_tile[s.grid];
         const int ntx = tiles_x(p, tile), nty = tiles_y(p, tile);
         if (s.tx < 0 || s.tx >= ntx || s.ty < 0 || s.ty >= nty) return "segment tile out of range";
         if (s.z0 < 0 || s.z1 > p.nz || s.z0 >= s.z1) return "segment z-range out of range";
@@ -707,18 +714,40 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
 
     std::vector<mpd::Segment> segs;
     std::vector<int> wg;
+    std::vector<int> grid_tile;
     if (plan) {
+        const int cols = plan->seg_cols == 0 ? 5 : plan->seg_cols;
         if (plan->tile < 1 || plan->tile > mpdata_tile_count() || plan->nwg < 1 || plan->nseg < 1 ||
-            !plan->seg || !plan->wg_begin || plan->reserved != 0)
+            !plan->seg || !plan->wg_begin || (cols != 5 && cols != 6))
             return fail_to(errbuf, MPDATA_EINVAL, "invalid plan header");
         e.tile = plan->tile;
+        grid_tile.assign(n, e.tile);
+        if (cols == 6) {
+            // per-grid launch shapes: one launch of the mixed family
+            if (e.tile != mpd::kMixedTiles[0] && e.tile != mpd::kMixedTiles[1])
+                return fail_to(errbuf, MPDATA_EINVAL, "a plan with per-grid shapes names tile 5 or 7");
+            e.variant |= mpd::kVariantMixed;
+            std::vector<int> seen_tile(n, 0);
+            for (int s = 0; s < plan->nseg; ++s) {
+                const int32_t *v = plan->seg + 6 * (size_t)s;
+                if (v[0] < 0 || v[0] >= n) return fail_to(errbuf, MPDATA_EINVAL, "plan: segment grid out of range");
+                if (v[5] != mpd::kMixedTiles[0] && v[5] != mpd::kMixedTiles[1])
+                    return fail_to(errbuf, MPDATA_EINVAL, "plan: segment shape must be tile 5 or 7");
+                if (seen_tile[v[0]] && seen_tile[v[0]] != v[5])
+                    return fail_to(errbuf, MPDATA_EINVAL, "plan: the segments of a grid share one shape");
+                seen_tile[v[0]] = v[5];
+            }
+            for (int g = 0; g < n; ++g)
+                if (seen_tile[g]) grid_tile[g] = seen_tile[g];
+        }
         if (!(e.dtype == MPDATA_FP32 ? mpd::step_kernel_ptr<float>(e.tile, e.variant)
                                      : mpd::step_kernel_ptr<double>(e.tile, e.variant)))
             return fail_to(errbuf, MPDATA_ENOTSUP, "no step kernel for this launch shape and variant");
         segs.resize(plan->nseg);
         for (int s = 0; s < plan->nseg; ++s) {
-            const int32_t *v = plan->seg + 5 * (size_t)s;
-            segs[s] = mpd::Segment{v[0], v[1], v[2], v[3], v[4], 0, 0, 0};
+            const int32_t *v = plan->seg + (size_t)cols * s;
+            const int shape = cols == 6 && v[5] == mpd::kMixedTiles[1] ? 1 : 0;
+            segs[s] = mpd::Segment{v[0], v[1], v[2], v[3], v[4], shape, 0, 0};
         }
         wg.assign(plan->wg_begin, plan->wg_begin + plan->nwg + 1);
     } else {
@@ -727,8 +756,9 @@ static int engine_init(Engine &e, char *errbuf, int n, const mpdata_params *para
         const int cus = device_cus();
         if (per < 1 || cus < 1) return fail_to(errbuf, MPDATA_EDEVICE, "occupancy query failed");
         default_plan(e.params, e.tile, per * cus, segs, wg);
+        grid_tile.assign(n, e.tile);
     }
-    if (const char *m = check_plan(e.params, e.tile, segs, wg))
+    if (const char *m = check_plan(e.params, grid_tile, segs, wg))
         return fail_to(errbuf, MPDATA_EINVAL, "plan: %s", m);
     if (e.iord > 2 && !(e.dtype == MPDATA_FP32 ? mpd::pass_kernel_ptr<float>(e.tile, e.variant, mpd::kPassHead)
                                                : mpd::pass_kernel_ptr<double>(e.tile, e.variant, mpd::kPassHead)))
@@ -1029,8 +1059,11 @@ int mpdata_occupancy(int32_t dtype, int32_t tile, int32_t bc, int32_t nonos, int
     if (dtype != MPDATA_FP64 && dtype != MPDATA_FP32) return MPDATA_EINVAL;
     if (tile == 0) tile = default_tile(dtype, bc);
     if (tile < 1 || tile > mpdata_tile_count()) return MPDATA_EINVAL;
-    const int per = wg_per_cu(dtype, tile, (bc == MPDATA_BC_OPEN ? mpd::kVariantOpen : 0) |
-                                               (nonos ? mpd::kVariantNonos : 0));
+    const int variant = (bc == MPDATA_BC_OPEN ? mpd::kVariantOpen : 0) | (nonos ? mpd::kVariantNonos : 0);
+    if (!(dtype == MPDATA_FP32 ? mpd::step_kernel_ptr<float>(tile, variant)
+                               : mpd::step_kernel_ptr<double>(tile, variant)))
+        return MPDATA_ENOTSUP;
+    const int per = wg_per_cu(dtype, tile, variant);
     const int c = device_cus();
     if (per < 1 || c < 1) return MPDATA_EDEVICE;
     if (per_cu) *per_cu = per;

@@ -27,9 +27,11 @@ template <typename T> struct PassIO {
 };
 
 // A piece of work of the persistent step kernel: output tile (tx, ty) of a
-// grid over the planes [z0, z1).
+// grid over the planes [z0, z1); in a launch that mixes region shapes,
+// shape = the index of the segment's region in that launch family (0 or 1),
+// else 0.
 struct Segment {
-    int grid, tx, ty, z0, z1, pad0, pad1, pad2;
+    int grid, tx, ty, z0, z1, shape, pad1, pad2;
 };
 
 // x-y region of one workgroup (output tile = region minus a 2-cell halo)
@@ -41,7 +43,15 @@ const TileShape *tile_shapes(int *count);
 
 // Kernel variants: open boundaries, limiter on, variable-sign option,
 // divergent-flow term, Courant numbers that change in time.
-enum { kVariantOpen = 1, kVariantNonos = 2, kVariantVsign = 4, kVariantDiv = 8, kVariantTvel = 16 };
+enum { kVariantOpen = 1, kVariantNonos = 2, kVariantVsign = 4, kVariantDiv = 8, kVariantTvel = 16,
+       kVariantMixed = 32 };
+
+// The launch family of kVariantMixed: one persistent launch in which every
+// segment names one of two regions of 768 threads (Segment::shape 0 and 1),
+// so that each grid of a batch can take the shape that suits its size.
+// Built for FP32 periodic grids without the variable-sign option or the
+// divergent-flow term.
+constexpr int kMixedTiles[2] = {5, 7};  // tile ids: 32x24 and 24x32 regions
 
 // The two time levels of the Courant numbers of one step of a single grid
 // whose velocity changes in time (variant kVariantTvel): u at the start of

@@ -59,6 +59,41 @@ __global__ __launch_bounds__(RX * RY) void step_kernel(const GridDesc<T> *__rest
     }
 }
 
+// Persistent step kernel of a launch that mixes region shapes: segment s
+// marches a 32x24 region (shape 0) or a 24x32 one (shape 1), both 768
+// threads; the two LDS layouts share one allocation.  FP32 periodic grids.
+template <bool NONOS>
+__global__ __launch_bounds__(768) void step_kernel_mixed(const GridDesc<float> *__restrict__ grids,
+                                                       const Segment *__restrict__ segs,
+                                                       const int *__restrict__ wg_begin, int flip,
+                                                       double eps, long long *__restrict__ seg_ticks,
+                                                       TvArgs<float> tv)
+{
+    (void)tv;
+    __shared__ union {
+        Smem<float, 32, 24, kModeStep, false> a;
+        Smem<float, 24, 32, kModeStep, false> b;
+    } sm;
+    // values a march reads before its own planes are written are finite:
+    // both layouts start cleared, and later hold only finite results
+    smem_clear(sm.a);
+    smem_clear(sm.b);
+    const int b = wg_begin[blockIdx.x], e = wg_begin[blockIdx.x + 1];
+    for (int s = b; s < e; ++s) {
+        const Segment sg = segs[s];
+        const long long t_start = seg_ticks ? (long long)wall_clock64() : 0;
+        const GridDesc<float> &g = grids[sg.grid];
+        if (sg.shape == 1)
+            march<float, 24, 32, false, false, NONOS, false, false, kModeStep>(
+                g, PassIO<float>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm.b);
+        else
+            march<float, 32, 24, false, false, NONOS, false, false, kModeStep>(
+                g, PassIO<float>{}, flip, sg.tx, sg.ty, sg.z0, sg.z1, eps, sm.a);
+        __syncthreads();
+        if (seg_ticks && threadIdx.x == 0) seg_ticks[s] = (long long)wall_clock64() - t_start;
+    }
+}
+
 // ======================================================= donor cell (iord 1)
 
 template <typename T, bool OPEN>
@@ -88,8 +123,10 @@ __global__ __launch_bounds__(256) void step_donor(DonorArgs<T> a)
 
 const TileShape *tile_shapes(int *count)
 {
+    // 24x32 (tile 7): FP32 only -- FP64 takes x-neighbours from the adjacent
+    // lanes, which needs rows that tile a wave of 64
     static const TileShape shapes[] = {
-        {64, 16}, {32, 32}, {64, 8}, {32, 16}, {32, 24}, {16, 16},
+        {64, 16}, {32, 32}, {64, 8}, {32, 16}, {32, 24}, {16, 16}, {24, 32},
     };
     *count = (int)(sizeof(shapes) / sizeof(shapes[0]));
     return shapes;
@@ -148,6 +185,16 @@ template <typename T, int RX, int RY> static const void *pick(int variant)
 
 template <typename T> const void *step_kernel_ptr(int tile, int variant)
 {
+    if (variant & kVariantMixed) {
+        // the mixed launch family: FP32, periodic, plain options
+        if constexpr (sizeof(T) == 4) {
+            if ((tile == kMixedTiles[0] || tile == kMixedTiles[1]) &&
+                !(variant & (kVariantOpen | kVariantVsign | kVariantDiv | kVariantTvel)))
+                return (variant & kVariantNonos) ? (const void *)step_kernel_mixed<true>
+                                                 : (const void *)step_kernel_mixed<false>;
+        }
+        return nullptr;
+    }
     switch (tile) {
     case 1: return pick<T, 64, 16>(variant);
     case 2: return pick<T, 32, 32>(variant);
@@ -155,6 +202,11 @@ template <typename T> const void *step_kernel_ptr(int tile, int variant)
     case 4: return pick<T, 32, 16>(variant);
     case 5: return pick<T, 32, 24>(variant);
     case 6: return pick<T, 16, 16>(variant);
+    case 7:
+        if constexpr (sizeof(T) == 4) {
+            if (!(variant & (kVariantVsign | kVariantDiv | kVariantTvel))) return pick<T, 24, 32>(variant);
+        }
+        return nullptr;
     default: return nullptr;
     }
 }

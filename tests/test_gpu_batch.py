@@ -166,3 +166,55 @@ def test_batch_with_options_matches_single_grid(orc, opts):
         want = orc.run(f.psi, f.u1, f.u2, f.u3, f.h, 3, **opts)
         assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), i
     b.close()
+
+
+def test_mixed_shapes_in_one_launch_same_bits():
+    """Per-grid launch shapes in one persistent launch (32x24 and 24x32
+    regions, a sixth plan column): every grid equals its single-grid run bit
+    for bit, whichever shape it takes; a grid whose segments name two shapes,
+    or a shape outside the family, is rejected."""
+    from paper_1507_01265_amd import _lib, autotune
+    from paper_1507_01265_amd.batch import Batch
+    fs = _grids(6, 1200, dtype=np.float32)
+    ref = [_single(f, 3, torch.float32) for f in fs]
+    shapes = [f.psi.shape for f in fs]
+    for choice in ([5, 7, 5, 7, 7, 5], [7] * 6):
+        segs = autotune.mixed_segments(shapes, choice)
+        owner, _ = autotune.lpt(segs[:, 4] - segs[:, 3], 41)
+        plan = (5, *autotune.plan_from_owner(segs, owner, 41))
+        b = Batch.from_numpy(fs, dtype=torch.float32, plan=plan)
+        b.step(3)
+        b.sync()
+        for i in range(len(fs)):
+            np.testing.assert_array_equal(b.psi(i).cpu().numpy(), ref[i])
+        ticks = b.profile_step()
+        assert len(ticks) == len(segs) and (ticks > 0).all()
+        b.close()
+    segs = autotune.mixed_segments(shapes, [5] * 6)
+    bad = segs.copy()
+    bad[0, 5] = 7  # grid 0 in two shapes
+    with pytest.raises(_lib.MpdataError):
+        Batch.from_numpy(fs, dtype=torch.float32, plan=(5, bad, np.array([0, len(bad)])))
+    bad = segs.copy()
+    bad[:, 5] = 2  # not a shape of the family
+    with pytest.raises(_lib.MpdataError):
+        Batch.from_numpy(fs, dtype=torch.float32, plan=(5, bad, np.array([0, len(bad)])))
+    with pytest.raises(_lib.MpdataError):  # FP64 has no mixed launch
+        Batch.from_numpy(_grids(6, 1200), dtype=torch.float64, plan=(5, segs, np.array([0, len(segs)])))
+
+
+def test_autotune_per_grid_shapes():
+    """With both 768-thread regions measured, the tuner also times the mixed
+    plan; whichever plan wins gives the single-grid bits."""
+    from paper_1507_01265_amd import autotune
+    from paper_1507_01265_amd.batch import Batch
+    fs = _grids(8, 1300, dtype=np.float32)
+    g = [tuple(torch.from_numpy(a).cuda() for a in (f.psi, f.u1, f.u2, f.u3, f.h)) for f in fs]
+    tuned = autotune.tune(g, tiles=[5, 7], steps=2, profiles=2)
+    assert any(e["tile"] == "mixed" for e in tuned.log)
+    b = Batch(g, plan=tuned.plan)
+    b.step(2)
+    b.sync()
+    for i, f in enumerate(fs):
+        np.testing.assert_array_equal(b.psi(i).cpu().numpy(), _single(f, 2, torch.float32))
+    b.close()

@@ -72,6 +72,8 @@ def test_parity_every_tile_ragged(orc, bc, nonos):
     want = oracle_run(orc, f, 4, nonos=nonos)
     first = None
     for tile in range(1, _lib.mpdata_tile_count() + 1):
+        if not _lib.mpdata_tile_built(_lib.MPDATA_FP64, tile):
+            continue  # tile 7 (24x32) is built for FP32 only
         print(f"tile {tile} bc {bc} nonos {nonos}", flush=True)
         got = gpu_run(f, 4, nonos=nonos, tile=tile)
         assert rel_linf(got, want) <= 1e-12, (tile, rel_linf(got, want))
