@@ -82,8 +82,7 @@ template <bool OPEN> __device__ __forceinline__ int face_hi(int i, int n)
 
 // ---------------------------------------------------------------- arithmetic
 
-template <typename T> __device__ __forceinline__ T pos(T x) { return fmax(x, T(0)); }
-template <typename T> __device__ __forceinline__ T neg(T x) { return fmin(x, T(0)); }
+// notation of the comments: pos(x) = max(x, 0), neg(x) = min(x, 0)
 
 // donor-cell flux through a face with lower value l, upper value r:
 // pos(c) l + neg(c) r, evaluated as c times the upwind value (the same
@@ -298,14 +297,12 @@ template <typename T> __device__ __forceinline__ T from_hi(T v) { return dpp<kDp
 // y-faces and h (needed one iteration ahead) ...
 template <typename T> struct PlaneA {
     T u1lo, u1hi, u2lo, u2hi, h;
-    T w1lo, w2lo;  // the lower faces' Courant numbers at the end of the step (TVEL)
 };
 // ... and psi^n and the Courant number of its lower z-face (needed two
 // iterations ahead; in a further corrective pass also the two cell arrays
 // bx, bn that bound the earlier iterates).
 template <typename T> struct PlaneB {
     T pn, u3lo, bx, bn;
-    T w3lo;  // the lower z-face's Courant number at the end of the step (TVEL)
 };
 
 // ================================================================ fused step
@@ -465,10 +462,6 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         const Rsrc u2p = plane_rsrc(g.u2, k, pc_u2);
         r.h = bload<T>(hp, b_c);
         r.u1lo = bload<T>(u1p, b_u1lo);
-        if constexpr (TVEL) {
-            r.w1lo = bload<T>(plane_rsrc(tv.w1, k, pc_u1), b_u1lo);
-            r.w2lo = bload<T>(plane_rsrc(tv.w2, k, pc_u2), OPXY ? b_u2lo : b_c);
-        }
         if (OPXY) {
             r.u1hi = bload<T>(u1p, b_u1hi);
             r.u2lo = bload<T>(u2p, b_u2lo);
@@ -487,7 +480,6 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         const Rsrc u3p = plane_rsrc(g.u3, kf, pc_cells);
         r.pn = bload<T>(pp, b_c);
         r.u3lo = bload<T>(u3p, b_c);
-        if constexpr (TVEL) r.w3lo = bload<T>(plane_rsrc(tv.w3, kf, pc_cells), b_c);
         if constexpr (kPass && NONOS) {
             r.bx = bload<T>(plane_rsrc(io.bmx, k, pc_cells), b_c);
             r.bn = bload<T>(plane_rsrc(io.bmn, k, pc_cells), b_c);
@@ -540,7 +532,10 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     // plane below it: the bounds at t-1 add only psi^n(t) to these
     T zmx_m1 = T(0), zmn_m1 = T(0);
     T u1_m1 = T(0), u2_m1 = T(0);               // lower-face Courant, plane t-1
-    T w1_m1 = T(0), w2_m1 = T(0);               // the same at the end of the step (TVEL)
+    // TVEL: plane of position t, for the end-of-step Courant numbers that
+    // S3 of iteration t reads (loaded at the top of the iteration, not held
+    // across iterations: the registers of the prefetch are all taken)
+    int kt = plane_of(t0);
     T rh_m1 = T(1), rh_m2 = T(1), rh_m3 = T(1); // 1/h of planes t-1 .. t-3
     // Own-column psi1 of planes t-1 .. t-3 and the Courant sums and h of plane
     // t-1 also sit in LDS (for the neighbours); the column keeps its own copy
@@ -568,6 +563,18 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         constexpr bool OZ = decltype(zopen)::value;
         constexpr int s0 = decltype(slot)::value;           // slot of plane t (held t-3)
         constexpr int s1 = (s0 + 2) % 3, s2 = (s0 + 1) % 3; // planes t-1, t-2
+        // end-of-step Courant numbers of the lower x/y faces of plane t-1 and
+        // of z-face t (TVEL), issued before the prefetch so that waiting for
+        // them in phase 2 does not wait for it
+        T w1_m1 = T(0), w2_m1 = T(0), w3_c = T(0);
+        if constexpr (TVEL) {
+            const int kp = OPZ ? clampi(t - 1, 0, nz - 1) : (kt == 0 ? nz - 1 : kt - 1);
+            const int kf = OPZ ? clampi(t, 0, nz) : kt;
+            w1_m1 = bload<T>(plane_rsrc(tv.w1, kp, pc_u1), b_u1lo);
+            w2_m1 = bload<T>(plane_rsrc(tv.w2, kp, pc_u2), OPXY ? b_u2lo : b_c);
+            w3_c = bload<T>(plane_rsrc(tv.w3, kf, pc_cells), b_c);
+            kt = OPZ ? clampi(t + 1, 0, nz - 1) : (kt + 1 == nz ? 0 : kt + 1);
+        }
         load_a(ka, nxA);
         load_b(kb, OZ ? zface_of(t + 2) : kb, nx2);
         ka = kb;
@@ -802,7 +809,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                                           c2_m1 + c2_c, av(Qb[q + cyp]) + av(qyp_),
                                           av(Qb[q + cym]) + av(qym_), eps, d_m1 + d_c);
             }
-            if constexpr (TVEL) v3 = v3 + T(0.5) * (cur.w3lo - cur.u3lo);
+            if constexpr (TVEL) v3 = v3 + T(0.5) * (w3_c - cur.u3lo);
             if (OZ && (t <= 0 || t >= nz)) v3 = T(0);
             if (NONOS) {
                 // ---- S4 bounds at plane p
@@ -842,11 +849,19 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             const L x_lo = L(fa1), x_hi = L(fa1_hi);
             const L y_lo = L(fa2), y_hi = L(sFA2[q + YP]);
             const L z_lo = L(fa3_m1), z_hi = L(fa3_c);
-            const L in = ((pos(x_lo) - neg(x_hi)) + (pos(y_lo) - neg(y_hi))) + (pos(z_lo) - neg(z_hi));
-            const L ou = ((pos(x_hi) - neg(x_lo)) + (pos(y_hi) - neg(y_lo))) + (pos(z_hi) - neg(z_lo));
+            // IN and OUT (the sums of the fluxes into and out of the cell):
+            // every face flux adds its magnitude to one of them, so with
+            // ab = sum |F| and nt = the net inflow (lower faces minus upper),
+            // IN = (ab + nt)/2 and OUT = (ab - nt)/2 -- 12 operations fewer than
+            // six max/min pairs (FP32 step 2.7 % faster, measured).  Where no
+            // face brings flux in, ab + nt is an exact zero (each term of nt is
+            // then the exact negation of the same term of ab), as is ab - nt
+            // where none takes flux out.
+            const L ab = ((fabs(x_lo) + fabs(x_hi)) + (fabs(y_lo) + fabs(y_hi))) + (fabs(z_lo) + fabs(z_hi));
+            const L nt = ((x_lo - x_hi) + (y_lo - y_hi)) + (z_lo - z_hi);
             // beta_up = (mx - psi1) h / (IN + eps), beta_dn = (psi1 - mn) h / (OUT + eps),
             // over the common denominator (IN + eps)(OUT + eps)
-            const L din = in + eps_l, dou = ou + eps_l;
+            const L din = fma(ab + nt, L(0.5), eps_l), dou = fma(ab - nt, L(0.5), eps_l);
             const L r = rcp_nr(din * dou) * L(h_m1);
             bu_m1 = F(fmin(L(1), ((L(mx) - L(p1_m1)) * dou) * r));
             bd_m1 = F(fmin(L(1), ((L(p1_m1) - L(mn)) * din) * r));
@@ -914,10 +929,6 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         zmn_m1 = zmn_c;
         u1_m1 = curA.u1lo;
         u2_m1 = curA.u2lo;
-        if constexpr (TVEL) {
-            w1_m1 = curA.w1lo;
-            w2_m1 = curA.w2lo;
-        }
         rh_m3 = rh_m2;
         rh_m2 = rh_m1;
         rh_m1 = rh_c;
