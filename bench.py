@@ -388,6 +388,8 @@ def bench_batched(args):
     restore()
     print("# tuning", file=sys.stderr, flush=True)
     tuned = autotune.tune(grids, steps=4, profiles=3)
+    for e in tuned.log:
+        print("# tune", json.dumps(e), file=sys.stderr, flush=True)
     b = Batch(grids, plan=tuned.plan)
     b.step(W)
     restore()
