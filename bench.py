@@ -120,13 +120,16 @@ SIMDS = 256 * 4
 CLOCK_GHZ = 2.4
 
 
+KERNEL_SOURCES = ("csrc/mpdata_march.h", "csrc/mpdata_step.hip", "build.py")
+
+
 def kernel_source_sha():
-    """sha256 of the step kernel's source: the march and the kernel file,
-    concatenated."""
+    """sha256 of what the step kernel is compiled from: the march, the kernel
+    file and the build script (its compiler flags), concatenated."""
     import hashlib
-    csrc = os.path.join(ROOT, "paper_1507_01265_amd", "csrc")
-    return hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                   for f in ("mpdata_march.h", "mpdata_step.hip"))).hexdigest()
+    pkg = os.path.join(ROOT, "paper_1507_01265_amd")
+    return hashlib.sha256(b"".join(open(os.path.join(pkg, f), "rb").read()
+                                   for f in KERNEL_SOURCES)).hexdigest()
 
 
 def profile_figures(workload):

@@ -16,6 +16,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmpdata.so")
+# Scheduling of the march kernels: the compiler's AMDGPU register-pressure
+# trackers leave fewer spills at the 168-VGPR limit of three waves per SIMD
+# (the time-dependent FP64 step: 8 VGPRs instead of 29, 15 % faster; the open
+# FP64 step: 9 instead of 36), and the strategy that keeps memory clauses
+# together makes the FP64 steps 1.5-2 % faster (measured; FP32 unchanged,
+# the ILP strategy slower).
+SCHED = ["-mllvm", "-amdgpu-use-amdgpu-trackers=1",
+         "-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]
 # (source, extra flags): the step kernels assume finite inputs (no NaN
 # semantics, so min/max need no operand canonicalisation) and contract a
 # product and a sum into an FMA only within one expression
@@ -24,8 +32,8 @@ LIB = os.path.join(HERE, "libmpdata.so")
 # differently in different copies, so that launch plans (which decide the
 # copy a plane lands in) would change bits.  The mass and validation kernels
 # keep IEEE semantics because they detect NaN/Inf.
-SOURCES = [("mpdata_step.hip", ["-fno-honor-nans", "-ffp-contract=on"]),
-           ("mpdata_pass.hip", ["-fno-honor-nans", "-ffp-contract=on"]),
+SOURCES = [("mpdata_step.hip", ["-fno-honor-nans", "-ffp-contract=on", *SCHED]),
+           ("mpdata_pass.hip", ["-fno-honor-nans", "-ffp-contract=on", *SCHED]),
            ("mpdata_reduce.hip", []), ("mpdata_abi.hip", [])]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
