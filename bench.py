@@ -120,16 +120,21 @@ SIMDS = 256 * 4
 CLOCK_GHZ = 2.4
 
 
-KERNEL_SOURCES = ("csrc/mpdata_march.h", "csrc/mpdata_step.hip", "build.py")
+def step_compile_flags():
+    """The compiler flags of the step kernel's source, as the build uses them."""
+    from paper_1507_01265_amd import build
+    extra = dict(build.SOURCES)["mpdata_step.hip"]
+    return " ".join([*build.FLAGS, *extra])
 
 
 def kernel_source_sha():
-    """sha256 of what the step kernel is compiled from: the march, the kernel
-    file and the build script (its compiler flags), concatenated."""
+    """sha256 of what the step kernel is compiled from: the march and the
+    kernel file, concatenated, followed by its compiler flags."""
     import hashlib
-    pkg = os.path.join(ROOT, "paper_1507_01265_amd")
-    return hashlib.sha256(b"".join(open(os.path.join(pkg, f), "rb").read()
-                                   for f in KERNEL_SOURCES)).hexdigest()
+    csrc = os.path.join(ROOT, "paper_1507_01265_amd", "csrc")
+    return hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                   for f in ("mpdata_march.h", "mpdata_step.hip"))
+                          + step_compile_flags().encode()).hexdigest()
 
 
 def profile_figures(workload):

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmpdata.so")
 # Scheduling of the march kernels: the compiler's AMDGPU register-pressure
 # trackers leave fewer spills at the 168-VGPR limit of three waves per SIMD
 # (the time-dependent FP64 step: 8 VGPRs instead of 29, 15 % faster; the open
-# FP64 step: 9 instead of 36), and the strategy that keeps memory clauses
+# FP64 step: 8 instead of 36), and the strategy that keeps memory clauses
 # together makes the FP64 steps 1.5-2 % faster (measured; FP32 unchanged,
 # the ILP strategy slower).
 SCHED = ["-mllvm", "-amdgpu-use-amdgpu-trackers=1",

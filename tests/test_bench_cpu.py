@@ -70,10 +70,13 @@ def test_timing_spread():
 
 def test_traffic_needs_the_current_kernel_source(tmp_path, monkeypatch):
     import hashlib
-    pkg = os.path.join(ROOT, "paper_1507_01265_amd")
-    sha = hashlib.sha256(b"".join(open(os.path.join(pkg, f), "rb").read()
-                                  for f in ("csrc/mpdata_march.h", "csrc/mpdata_step.hip",
-                                            "build.py"))).hexdigest()
+    from paper_1507_01265_amd import build
+    csrc = os.path.join(ROOT, "paper_1507_01265_amd", "csrc")
+    flags = " ".join([*build.FLAGS, *dict(build.SOURCES)["mpdata_step.hip"]])
+    assert "-amdgpu-use-amdgpu-trackers=1" in flags
+    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                  for f in ("mpdata_march.h", "mpdata_step.hip"))
+                         + flags.encode()).hexdigest()
     good = tmp_path / "good.md"
     good.write_text(f"kernel_source_sha256: {sha}\ntraffic_bytes_per_launch: 12345\n")
     stale = tmp_path / "stale.md"
