@@ -227,7 +227,9 @@ int mpdata_tile_info(int32_t id, int32_t *tx, int32_t *ty, int32_t *threads);
 int32_t mpdata_default_tile(int32_t dtype, int32_t bc);
 
 /* Resident workgroups of the step kernel for (dtype, tile, bc, nonos) on the
- * current device: *per_cu per compute unit, *cus compute units. */
+ * current device: *per_cu per compute unit, *cus compute units.
+ * MPDATA_EINVAL for an unknown dtype or tile id, MPDATA_ENOTSUP when no step
+ * kernel is built for that combination (tile 7 with FP64). */
 int mpdata_occupancy(int32_t dtype, int32_t tile, int32_t bc, int32_t nonos, int32_t *per_cu,
                      int32_t *cus);
 
