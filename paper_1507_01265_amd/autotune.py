@@ -13,7 +13,9 @@ Two decisions are made from measurements on the GPU:
   are per-block durations measured while all workgroups run together -- the
   paper's lesson that processing units sharing a chip must be benchmarked
   simultaneously, not one at a time (section 5.4) -- starting from a plan
-  placed with the static cost (planes + pipeline priming).
+  placed with the static cost (planes + pipeline priming).  A third
+  placement keeps every grid on one XCD (one L2).  All three are timed and
+  the fastest kept: which one wins depends on the shape (measured).
 
 The halo depth is fixed by the stencil (3 cells of psi^n per fused step).
 """
@@ -30,6 +32,7 @@ from . import _lib
 from .batch import Batch
 
 PRIMING = 4  # extra z-iterations of a march before its first output plane
+XCDS = 8     # workgroup w of a launch runs on XCD w mod 8 (each XCD has its own L2)
 
 
 def tiles_of(shape, tile):
@@ -62,6 +65,24 @@ def lpt(costs, nwg):
         loads[w] = load
         heapq.heappush(heap, (load, w))
     return owner, loads
+
+
+def xcd_affine(segs, costs, nwg, ngrids):
+    """Owner of each segment with every grid kept on one XCD: the grids are
+    dealt to the XCDs by LPT of their total cost, then each XCD's segments
+    by LPT over its workgroups (w mod XCDS == xcd), so a grid's tiles share
+    one L2."""
+    g = segs[:, 0]
+    costs = np.asarray(costs, dtype=np.float64)
+    grid_xcd, _ = lpt(np.bincount(g, weights=costs, minlength=ngrids), XCDS)
+    owner = np.empty(len(segs), dtype=np.int64)
+    for x in range(XCDS):
+        idx = np.nonzero(grid_xcd[g] == x)[0]
+        wgs = np.arange(x, nwg, XCDS)
+        if len(idx):
+            o, _ = lpt(costs[idx], len(wgs))
+            owner[idx] = wgs[o]
+    return owner
 
 
 def plan_from_owner(segs, owner, nwg):
@@ -163,14 +184,24 @@ def tune(grids, *, bc="periodic", nonos=True, eps=1e-15, tiles=None, steps=4, pr
         b.step(2)
         ms1 = time_steps(b, steps)
         b.close()
+        # the static placement with every grid on one XCD (its own L2)
+        ms2 = float("inf")
+        if nwg % XCDS == 0:
+            plan2 = (tile, *plan_from_owner(segs, xcd_affine(segs, static, nwg, len(grids)), nwg))
+            b = Batch(grids, plan=plan2, **opts)
+            b.step(2)
+            ms2 = time_steps(b, steps)
+            b.close()
         entry = dict(tile=tile, nwg=nwg, nseg=len(segs), ms_static=ms0, ms_measured=ms1,
+                     ms_xcd=ms2,
                      makespan_static_ticks=float(loads0.max()),
                      makespan_measured_ticks=float(loads1.max()),
                      mean_load_ticks=float(measured.sum() / nwg))
         log.append(entry)
         if verbose:
             print("tune", entry, flush=True)
-        for ms, plan, mk in ((ms0, plan0, loads0.max()), (ms1, plan1, loads1.max())):
+        cands = [(ms0, plan0), (ms1, plan1)] + ([(ms2, plan2)] if nwg % XCDS == 0 else [])
+        for ms, plan in cands:
             if best is None or ms < best.ms_per_step:
                 best = Tuned(tile, plan, ms, float(loads0.max()), float(loads1.max()), log)
     if (dtype == torch.float32 and bc == "periodic" and not vsign and not div
