@@ -15,7 +15,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <new>
+#include <queue>
 #include <vector>
 
 #include "../../include/mpdata.h"
@@ -232,13 +234,89 @@ void share_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
 
 // Default plan: the whole-tile plan unless its makespan exceeds the
 // contiguous-share plan's by more than the L2 gain of aligned marches.
+// Longest-processing-time-first over `cost`, onto the workgroups `wgs`:
+// each item (in order of decreasing cost, ties in list order) goes to the
+// workgroup with the least load so far (ties to the lower id).  Returns the
+// owner of every item.
+std::vector<int> lpt_assign(const std::vector<long long> &cost, const std::vector<int> &wgs)
+{
+    std::vector<int> order(cost.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    using Slot = std::pair<long long, int>;  // (load, workgroup)
+    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+    for (int w : wgs) heap.push({0, w});
+    std::vector<int> owner(cost.size(), 0);
+    for (int i : order) {
+        Slot sl = heap.top();
+        heap.pop();
+        owner[i] = sl.second;
+        heap.push({sl.first + cost[i], sl.second});
+    }
+    return owner;
+}
+
+// Whole tiles placed by LPT with every grid on one XCD (one L2): the grids
+// are dealt to the XCDs by LPT of their work (planes plus pipeline fill of
+// every tile), then each XCD's tiles by LPT over its workgroups (w % kXcds
+// == x).  For batches of uneven grids, which the round-robin deal leaves
+// unbalanced.
+void lpt_xcd_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
+                  std::vector<mpd::Segment> &segs, std::vector<int> &wg_begin)
+{
+    const int ng = (int)grids.size();
+    std::vector<long long> grid_cost(ng);
+    for (int g = 0; g < ng; ++g)
+        grid_cost[g] = (long long)tiles_x(grids[g], tile) * tiles_y(grids[g], tile) *
+                       (grids[g].nz + kPipelineFill);
+    std::vector<int> xcds(kXcds);
+    for (int x = 0; x < kXcds; ++x) xcds[x] = x;
+    const std::vector<int> grid_xcd = lpt_assign(grid_cost, xcds);
+    std::vector<std::vector<mpd::Segment>> per(nwg);
+    for (int x = 0; x < kXcds; ++x) {
+        std::vector<mpd::Segment> tl;
+        std::vector<long long> cost;
+        for (int g = 0; g < ng; ++g) {
+            if (grid_xcd[g] != x) continue;
+            const int ntx = tiles_x(grids[g], tile), nty = tiles_y(grids[g], tile);
+            for (int ty = 0; ty < nty; ++ty)
+                for (int tx = 0; tx < ntx; ++tx) {
+                    tl.push_back(mpd::Segment{g, tx, ty, 0, grids[g].nz, 0, 0, 0});
+                    cost.push_back(grids[g].nz + kPipelineFill);
+                }
+        }
+        std::vector<int> wgs;
+        for (int w = x; w < nwg; w += kXcds) wgs.push_back(w);
+        const std::vector<int> owner = lpt_assign(cost, wgs);
+        for (size_t i = 0; i < tl.size(); ++i) per[owner[i]].push_back(tl[i]);
+    }
+    segs.clear();
+    wg_begin.assign(nwg + 1, 0);
+    for (int w = 0; w < nwg; ++w) {
+        wg_begin[w] = (int)segs.size();
+        segs.insert(segs.end(), per[w].begin(), per[w].end());
+    }
+    wg_begin[nwg] = (int)segs.size();
+}
+
+// The library's plan: whole tiles (dealt round-robin, or by LPT with every
+// grid on one XCD when nwg is a multiple of the XCD count and that balances
+// better) unless they balance worse than 1.1x the makespan of equal shares
+// of planes.
 void default_plan(const std::vector<mpdata_params> &grids, int tile, int nwg,
                   std::vector<mpd::Segment> &segs, std::vector<int> &wg_begin)
 {
-    std::vector<mpd::Segment> s2;
-    std::vector<int> w2;
+    std::vector<mpd::Segment> s2, s3;
+    std::vector<int> w2, w3;
     share_plan(grids, tile, nwg, segs, wg_begin);
     whole_tile_plan(grids, tile, nwg, s2, w2);
+    if (nwg % kXcds == 0 && grids.size() > 1) {
+        lpt_xcd_plan(grids, tile, nwg, s3, w3);
+        if (plan_makespan(s3, w3) < plan_makespan(s2, w2)) {
+            s2.swap(s3);
+            w2.swap(w3);
+        }
+    }
     if (plan_makespan(s2, w2) * 10 <= plan_makespan(segs, wg_begin) * 11) {
         segs.swap(s2);
         wg_begin.swap(w2);
