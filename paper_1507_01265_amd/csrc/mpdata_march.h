@@ -323,6 +323,10 @@ template <typename T> struct PlaneB {
 // kModeMid writes its velocity and the running bounds on.
 enum { kModeStep = 0, kModeHead = 1, kModeMid = 2, kModeLast = 3 };
 
+// Which stages an iteration of the march runs: all of them, or the reduced
+// sets of a segment's first, second and last iteration.
+enum { kPartFull = 0, kPartFirst = 1, kPartSecond = 2, kPartLast = 3 };
+
 // LDS planes of one workgroup (each padded by one cell on every side).
 template <typename T, int RX, int RY, int MODE, bool DIVP = false> struct Smem {
     static constexpr int PX = RX + 2, PP = PX * (RY + 2);
@@ -559,7 +563,18 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
 
     // zopen: the z-boundary handling of this iteration (OPZ, or false on the
     // planes away from an open top and bottom, where it is the identity)
-    auto iter = [&](const int t, auto slot, auto zopen) {
+    // FP32 runs the reduced first, second and last iterations (below); the
+    // FP64 kernels, at their register limit, spilled with them (22 VGPRs in
+    // the periodic limiter kernel), so they run every iteration in full
+    constexpr bool kTrimFill = sizeof(T) == 4;
+    // part: which stages the iteration runs.  A segment's first iteration
+    // (t = z0 - 2) needs only psi1 of its plane (later iterations read it),
+    // its second (t = z0 - 1) psi1 and the pseudo-velocity on z-face t (the
+    // limiter factors of plane z0 - 1 need it), its last (t = z1 + 2) only S7
+    // of plane z1 - 1: every other result of those iterations belongs to a
+    // plane no output of the segment depends on.
+    auto iter = [&](const int t, auto slot, auto zopen, auto part) {
+        constexpr int P = decltype(part)::value;
         constexpr bool OZ = decltype(zopen)::value;
         constexpr int s0 = decltype(slot)::value;           // slot of plane t (held t-3)
         constexpr int s1 = (s0 + 2) % 3, s2 = (s0 + 1) % 3; // planes t-1, t-2
@@ -567,18 +582,22 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         // of z-face t (TVEL), issued before the prefetch so that waiting for
         // them in phase 2 does not wait for it
         T w1_m1 = T(0), w2_m1 = T(0), w3_c = T(0);
-        if constexpr (TVEL) {
+        if constexpr (TVEL && P != kPartLast) {
             const int kp = OPZ ? clampi(t - 1, 0, nz - 1) : (kt == 0 ? nz - 1 : kt - 1);
             const int kf = OPZ ? clampi(t, 0, nz) : kt;
-            w1_m1 = bload<T>(plane_rsrc(tv.w1, kp, pc_u1), b_u1lo);
-            w2_m1 = bload<T>(plane_rsrc(tv.w2, kp, pc_u2), OPXY ? b_u2lo : b_c);
-            w3_c = bload<T>(plane_rsrc(tv.w3, kf, pc_cells), b_c);
+            if constexpr (P == kPartFull) {
+                w1_m1 = bload<T>(plane_rsrc(tv.w1, kp, pc_u1), b_u1lo);
+                w2_m1 = bload<T>(plane_rsrc(tv.w2, kp, pc_u2), OPXY ? b_u2lo : b_c);
+            }
+            if constexpr (P != kPartFirst) w3_c = bload<T>(plane_rsrc(tv.w3, kf, pc_cells), b_c);
             kt = OPZ ? clampi(t + 1, 0, nz - 1) : (kt + 1 == nz ? 0 : kt + 1);
         }
-        load_a(ka, nxA);
-        load_b(kb, OZ ? zface_of(t + 2) : kb, nx2);
-        ka = kb;
-        kb = OZ ? clampi(t + 3, 0, nz - 1) : (kb + 1 == nz ? 0 : kb + 1);
+        if constexpr (P != kPartLast) {
+            load_a(ka, nxA);
+            load_b(kb, OZ ? zface_of(t + 2) : kb, nx2);
+            ka = kb;
+            kb = OZ ? clampi(t + 3, 0, nz - 1) : (kb + 1 == nz ? 0 : kb + 1);
+        }
         __syncthreads();  // (B) psi^n(t), sums/h of t-1, corrective y-fluxes of t-3 are visible
         // own-column values of planes t-1 .. t-3
         const T p1_m1 = r_p1_m1, p1_m2 = r_p1_m2, p1_m3 = r_p1_m3;
@@ -588,11 +607,11 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         // limiter factors of plane t-2 (computed last iteration) for the
         // neighbours' corrective pass after (F); their previous contents were
         // last read before (B)
-        if (NONOS) {
+        if (NONOS && P == kPartFull) {
             sBU[q] = bu_m2;
             sBD[q] = bd_m2;
         }
-        {
+        if constexpr (P == kPartFull || P == kPartLast) {
             // ---- S7 at plane t-3 (its corrective fluxes were stored last iteration)
             T fc1hi;
             if constexpr (kDpp) fc1hi = from_hi(fc1_m3);
@@ -602,6 +621,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             const T res = p1_m3 - (((fc1hi - fc1_m3) + (fc2hi - fc2lo)) + (fc3_m2 - fc3_m3)) * rh_m3;
             bstore_if<kIssueAll, T>(psi_out, t - 3, t >= z0 + 3 && t <= tend, pc_cells, b_c, is_out, res);
         }
+        if constexpr (P == kPartLast) return;
 
         const bool own_plane = t >= z0 && t < z1;  // plane t is one of the segment's
         T p1_c, zmx_c, zmn_c, rh_c, f3hi = T(0);
@@ -657,7 +677,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             T xh, xc2, xc3, xqyp, xqym, xlo, xd; // cell a of the lower x-face
             T yxp, yxm, yh, yc3, yc1, ylo, yd;   // cell a of the lower y-face
         } e{};
-        if constexpr (kEarlyS3) {
+        if constexpr (kEarlyS3 && P != kPartFirst) {
             const bool clo = OZ && t - 1 <= 0;
             const T *Qc = sQ[s1];
             const T *Qlo = clo ? sQ[s1] : sQ[s2];
@@ -671,7 +691,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         }
         __syncthreads();  // (D) psi1(t) and the limiter factors of t-2 are visible
 
-        T v1, v2, v3, fa1 = T(0), fa2 = T(0), fa3_c = T(0);
+        T v1 = T(0), v2 = T(0), v3 = T(0), fa1 = T(0), fa2 = T(0), fa3_c = T(0);
         // FP32: the LDS operands of S6 at plane t-2 (psi1 and the limiter
         // factors of the x- and y-neighbours), written before (D), are read
         // during the arithmetic of this phase instead of after (F) (1.6 %
@@ -681,7 +701,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         F bu6_y = F(1), bd6_y = F(1), bu6_x = F(1), bd6_x = F(1);
         T pc_xlo = T(0), p2_xm = T(0);
         T mx = T(0), mn = T(0);
-        {
+        if constexpr (P != kPartFirst) {
             // ---- S3 at plane p = t-1 (lower x- and y-faces) and on face t
             const int p = t - 1;
             const bool clo = OZ && p <= 0, chi = OZ && p >= nz - 1;
@@ -719,7 +739,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                 qxp_ = Qc[q + cxp];
                 qxm_ = Qc[q + cxm];
             }
-            {
+            if constexpr (P == kPartFull) {
                 // x-face between a = (lx-1) and b = own; transverse axes y then z
                 T h_a, c2_a, c3_a, qyp_a, qym_a, phi_a, plo_a, d_a = T(0);
                 if constexpr (kDpp) {
@@ -751,7 +771,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             // the compiler hoist the y-face's LDS reads (3.5 % faster step,
             // measured)
             if constexpr (kFenceFaces) __builtin_amdgcn_sched_barrier(0);
-            {
+            if constexpr (P == kPartFull) {
                 // y-face between a = (ly-1) and b = own; transverse axes z then x
                 T d_ya = T(0);
                 if constexpr (kEarlyS3) {
@@ -781,7 +801,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                 if (zero_v2) v2 = T(0);
             }
             if constexpr (kFenceFaces) __builtin_amdgcn_sched_barrier(0);
-            if constexpr (!kDpp) {
+            if constexpr (!kDpp && P == kPartFull) {
                 q6_y = sQ[s2][q + YM];
                 if (NONOS) {
                     bu6_y = sBU[q + YM];
@@ -811,7 +831,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             }
             if constexpr (TVEL) v3 = v3 + T(0.5) * (w3_c - cur.u3lo);
             if (OZ && (t <= 0 || t >= nz)) v3 = T(0);
-            if (NONOS) {
+            if (NONOS && P == kPartFull) {
                 // ---- S4 bounds at plane p
                 if constexpr (kPass) {
                     // the running bounds of plane t complete the 7 points (at
@@ -830,18 +850,20 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                 fa2 = donor(qd, p1_m1, v2);
                 if constexpr (!kDpp) sFA1[q] = fa1;
                 sFA2[q] = fa2;
-                fa3_c = donor(p1_m1, p1_c, v3);
             }
+            if (NONOS) fa3_c = donor(p1_m1, p1_c, v3);
         }
         // psi^n of plane t+1: every read of plane t in sP happened before (D)
         if constexpr (!kPass) {
             sP[q] = nx1.pn;
             if (has_ring) sP[p_ring] = rng;
         }
-        __syncthreads();  // (F) antidiffusive fluxes visible
+        // the first two iterations of a segment compute no limiter factors or
+        // corrective fluxes, and so need no (F)
+        if constexpr (P == kPartFull) __syncthreads();  // (F) antidiffusive fluxes visible
 
         F bu_m1 = F(1), bd_m1 = F(1);
-        if (NONOS) {
+        if (NONOS && P == kPartFull) {
             // ---- S5 limiter factors at plane t-1
             T fa1_hi;
             if constexpr (kDpp) fa1_hi = from_hi(fa1);
@@ -867,8 +889,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             bd_m1 = F(fmin(L(1), ((L(p1_m1) - L(mn)) * din) * r));
         }
 
-        T fc1_r, fc2_r, fc3_m1;
-        {
+        T fc1_r = T(0), fc2_r = T(0), fc3_m1 = T(0);
+        if constexpr (P == kPartFull) {
             // ---- S6 + corrective fluxes at plane r = t-2 (lower faces) and on face t-1;
             // the y-fluxes of t-3 in sFC2 were read before (D)
             T vt1 = v1_m2, vt2 = v2_m2, vt3 = v3_m1;
@@ -903,7 +925,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             fc3_m1 = donor(p1_m2, p1_m1, vt3);
         }
         // sums/h of plane t for the next iteration: the reads of plane t-1
-        // happened before (F)
+        // happened before (F) (the first two iterations of a segment do not
+        // read them)
         sC1[q] = c1_c;
         if constexpr (!kDpp) sC2[q] = c2_c;
         sC3[q] = c3_c;
@@ -958,9 +981,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         nx1 = nx2;
     };
 
-    // Unrolled by three so the psi1 planes sit in fixed slots (slot of plane
-    // t = (t - t0 + shift) mod 3); the iteration count modulo three is run
-    // first, in the last slots, so that no iteration is wasted.
+    // Unrolled by three so the psi1 planes sit in fixed slots: the slot of
+    // position t is (t - t0 + shift) mod 3, with shift chosen so that the
+    // last iteration takes slot 2.
     // With an open top and bottom, groups of three iterations t in
     // [2, nz - 4] take the code without the z-boundary handling: every
     // z-boundary test of such an iteration is false, and the planes it loads
@@ -969,33 +992,84 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     using S1 = std::integral_constant<int, 1>;
     using S2 = std::integral_constant<int, 2>;
     using ZO = std::bool_constant<OPZ>;
+    using Full = std::integral_constant<int, kPartFull>;
+    const int n_iter = tend - t0 + 1;  // z1 - z0 + 5 >= 6
     int t = t0;
-    switch ((tend - t0 + 1) % 3) {
-    case 2:
-        iter(t++, S1{}, ZO{});
-        [[fallthrough]];
-    case 1:
-        iter(t++, S2{}, ZO{});
-        break;
-    default:
-        break;
-    }
-    if constexpr (OPZ) {
-        for (; t <= tend && t < 2; t += 3) {
-            iter(t, S0{}, ZO{});
-            iter(t + 1, S1{}, ZO{});
-            iter(t + 2, S2{}, ZO{});
+    if constexpr (kTrimFill) {
+        // the first two iterations and the last one run their reduced parts;
+        // the iterations between them run their count modulo three first,
+        // then groups of three (slots 2, 0, 1)
+        using First = std::integral_constant<int, kPartFirst>;
+        using Second = std::integral_constant<int, kPartSecond>;
+        using Last = std::integral_constant<int, kPartLast>;
+        switch (n_iter % 3) {
+        case 0:  // shift 0
+            iter(t, S0{}, ZO{}, First{});
+            iter(t + 1, S1{}, ZO{}, Second{});
+            t += 2;
+            break;
+        case 2:  // shift 1
+            iter(t, S1{}, ZO{}, First{});
+            iter(t + 1, S2{}, ZO{}, Second{});
+            iter(t + 2, S0{}, ZO{}, Full{});
+            iter(t + 3, S1{}, ZO{}, Full{});
+            t += 4;
+            break;
+        default:  // 1: shift 2
+            iter(t, S2{}, ZO{}, First{});
+            iter(t + 1, S0{}, ZO{}, Second{});
+            iter(t + 2, S1{}, ZO{}, Full{});
+            t += 3;
+            break;
         }
-        for (; t <= tend && t + 2 <= nz - 4; t += 3) {
-            iter(t, S0{}, std::false_type{});
-            iter(t + 1, S1{}, std::false_type{});
-            iter(t + 2, S2{}, std::false_type{});
+        if constexpr (OPZ) {
+            for (; t < tend && t < 2; t += 3) {
+                iter(t, S2{}, ZO{}, Full{});
+                iter(t + 1, S0{}, ZO{}, Full{});
+                iter(t + 2, S1{}, ZO{}, Full{});
+            }
+            for (; t < tend && t + 2 <= nz - 4; t += 3) {
+                iter(t, S2{}, std::false_type{}, Full{});
+                iter(t + 1, S0{}, std::false_type{}, Full{});
+                iter(t + 2, S1{}, std::false_type{}, Full{});
+            }
         }
-    }
-    for (; t <= tend; t += 3) {
-        iter(t, S0{}, ZO{});
-        iter(t + 1, S1{}, ZO{});
-        iter(t + 2, S2{}, ZO{});
+        for (; t < tend; t += 3) {
+            iter(t, S2{}, ZO{}, Full{});
+            iter(t + 1, S0{}, ZO{}, Full{});
+            iter(t + 2, S1{}, ZO{}, Full{});
+        }
+        iter(tend, S2{}, ZO{}, Last{});
+    } else {
+        // every iteration runs all stages; the iteration count modulo three
+        // is run first, in the last slots
+        switch (n_iter % 3) {
+        case 2:
+            iter(t++, S1{}, ZO{}, Full{});
+            [[fallthrough]];
+        case 1:
+            iter(t++, S2{}, ZO{}, Full{});
+            break;
+        default:
+            break;
+        }
+        if constexpr (OPZ) {
+            for (; t <= tend && t < 2; t += 3) {
+                iter(t, S0{}, ZO{}, Full{});
+                iter(t + 1, S1{}, ZO{}, Full{});
+                iter(t + 2, S2{}, ZO{}, Full{});
+            }
+            for (; t <= tend && t + 2 <= nz - 4; t += 3) {
+                iter(t, S0{}, std::false_type{}, Full{});
+                iter(t + 1, S1{}, std::false_type{}, Full{});
+                iter(t + 2, S2{}, std::false_type{}, Full{});
+            }
+        }
+        for (; t <= tend; t += 3) {
+            iter(t, S0{}, ZO{}, Full{});
+            iter(t + 1, S1{}, ZO{}, Full{});
+            iter(t + 2, S2{}, ZO{}, Full{});
+        }
     }
 }
 
