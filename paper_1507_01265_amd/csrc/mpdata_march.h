@@ -239,23 +239,20 @@ template <typename T> __device__ __forceinline__ void bstore(Rsrc r, unsigned by
 constexpr unsigned kOobOffset = 0x80000000u;
 
 // Store into plane `plane` of an array (when the workgroup-uniform plane_ok
-// holds) for the lanes where lane_ok.  ISSUE_ALL: every lane issues it, a
-// disabled lane at kOobOffset (plane 0 when plane_ok fails), so that no
-// branch makes the number of memory operations a wave has in flight depend
-// on its lanes: the counter waits the compiler places before the use of a
-// prefetched value then stop at that value's load, not at the prefetches
-// issued after it (measured: periodic grids 1.5 % faster in FP64, 3 % in
-// FP32).  Open grids keep the branch: their kernels, which spill, ran 13 %
-// slower with it in FP64.
-template <bool ISSUE_ALL, typename T>
+// holds) for the lanes where lane_ok.  Every lane issues it, a disabled lane
+// at kOobOffset (plane 0 when plane_ok fails), so that no branch makes the
+// number of memory operations a wave has in flight depend on its lanes: the
+// counter waits the compiler places before the use of a prefetched value
+// then stop at that value's load, not at the prefetches issued after it
+// (measured: periodic grids 1.5 % faster in FP64, 3 % in FP32; open grids
+// 1.5 % (FP64) and 0.8 % (FP32) once their kernels stopped spilling much --
+// with 36 spilled VGPRs the open FP64 kernel had run 13 % slower with it).
+template <typename T>
 __device__ __forceinline__ void bstore_if(T *base, int plane, bool plane_ok, unsigned plane_elems,
                                           unsigned byte_off, bool lane_ok, T v)
 {
-    if constexpr (ISSUE_ALL)
-        bstore<T>(plane_rsrc<T>(base, plane_ok ? plane : 0, plane_elems),
-                  plane_ok && lane_ok ? byte_off : kOobOffset, v);
-    else if (plane_ok && lane_ok)
-        bstore<T>(plane_rsrc<T>(base, plane, plane_elems), byte_off, v);
+    bstore<T>(plane_rsrc<T>(base, plane_ok ? plane : 0, plane_elems),
+              plane_ok && lane_ok ? byte_off : kOobOffset, v);
 }
 
 // Lane exchange along x inside a wave.  A workgroup's rows are RX lanes long
@@ -369,7 +366,6 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                                       const TvArgs<T> &tv = TvArgs<T>{})
 {
     static_assert(!TVEL || MODE == kModeStep, "the time-variation term belongs to the fused step");
-    constexpr bool kIssueAll = !OPZ;  // memory operations issued by every lane (bstore_if)
     constexpr bool kPass = MODE >= kModeMid;                      // S1 replaced by a load
     constexpr bool kOuts = MODE == kModeHead || MODE == kModeMid; // velocity + bounds out
     using L = double;  // limiter precision (both variants)
@@ -491,14 +487,11 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     };
     // The ring threads load their ring cell of a plane late in the
     // iteration before it is stored (it is not held across the heavy phase).
-    // On periodic grids issued by every lane (the others read at kOobOffset
-    // and get zero), so that it leaves no branch around a memory operation
-    // (see bstore_if).
+    // Issued by every lane (the others read at kOobOffset and get zero), so
+    // that it leaves no branch around a memory operation (see bstore_if).
     auto load_ring = [&](int k) {
         if constexpr (kPass) return T(0);
-        else if constexpr (kIssueAll)
-            return bload<T>(plane_rsrc(psi_in, k, pc_cells), has_ring ? b_ring : kOobOffset);
-        else return has_ring ? bload<T>(plane_rsrc(psi_in, k, pc_cells), b_ring) : T(0);
+        else return bload<T>(plane_rsrc(psi_in, k, pc_cells), has_ring ? b_ring : kOobOffset);
     };
 
     const int t0 = z0 - 2, tend = z1 + 2;
@@ -619,7 +612,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             const T fc2hi = sFC2[q + YP];
             const T fc2lo = fc2_m3;
             const T res = p1_m3 - (((fc1hi - fc1_m3) + (fc2hi - fc2lo)) + (fc3_m2 - fc3_m3)) * rh_m3;
-            bstore_if<kIssueAll, T>(psi_out, t - 3, t >= z0 + 3 && t <= tend, pc_cells, b_c, is_out, res);
+            bstore_if<T>(psi_out, t - 3, t >= z0 + 3 && t <= tend, pc_cells, b_c, is_out, res);
         }
         if constexpr (P == kPartLast) return;
 
@@ -636,8 +629,8 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             zmn_c = fmin(fmin(fmin(sPm[q + cxm], sPm[q + cxp]), fmin(sPm[q + cym], sPm[q + cyp])),
                          zlo ? m_c : fmin(m_c, m_m1));
             if constexpr (MODE == kModeMid && NONOS) {
-                bstore_if<kIssueAll, T>(io.mx, t, own_plane, pc_cells, b_c, is_out, M_c);
-                bstore_if<kIssueAll, T>(io.mn, t, own_plane, pc_cells, b_c, is_out, m_c);
+                bstore_if<T>(io.mx, t, own_plane, pc_cells, b_c, is_out, M_c);
+                bstore_if<T>(io.mn, t, own_plane, pc_cells, b_c, is_out, m_c);
             }
         } else {
             // ---- S1+S2 at plane t
@@ -654,7 +647,7 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             zmn_c = fmin(fmin(fmin(pL, pR), fmin(pD, pU)), zlo ? cur.pn : fmin(cur.pn, pn_m1));
             if constexpr (MODE == kModeHead && NONOS) {
                 // psi1 for the next pass's bounds (psi^n stays in the input)
-                bstore_if<kIssueAll, T>(io.mx, t, own_plane, pc_cells, b_c, is_out, p1_c);
+                bstore_if<T>(io.mx, t, own_plane, pc_cells, b_c, is_out, p1_c);
             }
         }
         sQ[s0][q] = p1_c;  // psi1(t-3) of this slot was last read before (B)
@@ -911,9 +904,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
                 // z-faces (face nz from the segment that ends there)
                 const int r = t - 2, f = t - 1;
                 const bool r_ok = r >= z0 && r < z1;
-                bstore_if<kIssueAll, T>(io.w1, r, r_ok, pc_u1, b_w1, w1_lane, vt1);
-                bstore_if<kIssueAll, T>(io.w2, r, r_ok, pc_u2, b_w2, w2_lane, vt2);
-                bstore_if<kIssueAll, T>(io.w3, f, (f >= z0 && f < z1) || (f == nz && z1 == nz), pc_cells, b_c,
+                bstore_if<T>(io.w1, r, r_ok, pc_u1, b_w1, w1_lane, vt1);
+                bstore_if<T>(io.w2, r, r_ok, pc_u2, b_w2, w2_lane, vt2);
+                bstore_if<T>(io.w3, f, (f >= z0 && f < z1) || (f == nz && z1 == nz), pc_cells, b_c,
                              is_out, vt3);
             }
             if constexpr (!kDpp) p2_xm = q6_x;
