@@ -116,6 +116,21 @@ def test_degenerate_shapes(orc, shape, bc):
     assert rel_linf(got, want) <= 1e-12
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 5, 3), (3, 1, 66), (4, 17, 9), (5, 30, 41),
+                                   (6, 23, 33)])
+@pytest.mark.parametrize("bc", [0, 1], ids=["periodic", "open"])
+def test_degenerate_shapes_fp32(orc, shape, bc):
+    """FP32 marches run a segment's first two iterations and its last one
+    reduced; columns of 1 to 6 planes take every arrangement of those
+    iterations (the iteration count z1 - z0 + 5 in each residue mod 3), with
+    the limiter and without it, against the oracle on the same FP32 inputs."""
+    g = inputs.random_smooth(131 + shape[0], shape, bc=bc, cmax=0.15).astype(np.float32)
+    for nonos in (True, False):
+        want = oracle_run(orc, g.as_f64(), 3, nonos=nonos)
+        got = gpu_run(g, 3, dtype=torch.float32, nonos=nonos)
+        check_fp32(got, want, f"{shape} nonos={nonos}")
+
+
 @pytest.mark.parametrize("steps", [0, 1, 3])
 def test_step_counts(orc, steps):
     """Odd counts end with a copy from the workspace; 0 is a no-op."""
