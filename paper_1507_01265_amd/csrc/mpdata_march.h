@@ -557,8 +557,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
     // zopen: the z-boundary handling of this iteration (OPZ, or false on the
     // planes away from an open top and bottom, where it is the identity)
     // FP32 runs the reduced first, second and last iterations (below); the
-    // FP64 kernels, at their register limit, spilled with them (22 VGPRs in
-    // the periodic limiter kernel), so they run every iteration in full
+    // FP64 kernels, at their register limit, spilled with the first two
+    // (22 VGPRs in the periodic limiter kernel) and run only the last one
+    // reduced
     constexpr bool kTrimFill = sizeof(T) == 4;
     // part: which stages the iteration runs.  A segment's first iteration
     // (t = z0 - 2) needs only psi1 of its plane (later iterations read it),
@@ -1034,8 +1035,9 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
         }
         iter(tend, S2{}, ZO{}, Last{});
     } else {
-        // every iteration runs all stages; the iteration count modulo three
-        // is run first, in the last slots
+        // every iteration but the last runs all stages; the iteration count
+        // modulo three is run first, in the last slots, and the last group
+        // outside the loops (its third iteration reduced)
         switch (n_iter % 3) {
         case 2:
             iter(t++, S1{}, ZO{}, Full{});
@@ -1047,22 +1049,25 @@ __device__ __forceinline__ void march(const GridDesc<T> &g, const PassIO<T> &io,
             break;
         }
         if constexpr (OPZ) {
-            for (; t <= tend && t < 2; t += 3) {
+            for (; t + 2 < tend && t < 2; t += 3) {
                 iter(t, S0{}, ZO{}, Full{});
                 iter(t + 1, S1{}, ZO{}, Full{});
                 iter(t + 2, S2{}, ZO{}, Full{});
             }
-            for (; t <= tend && t + 2 <= nz - 4; t += 3) {
+            for (; t + 2 < tend && t + 2 <= nz - 4; t += 3) {
                 iter(t, S0{}, std::false_type{}, Full{});
                 iter(t + 1, S1{}, std::false_type{}, Full{});
                 iter(t + 2, S2{}, std::false_type{}, Full{});
             }
         }
-        for (; t <= tend; t += 3) {
+        for (; t + 2 < tend; t += 3) {
             iter(t, S0{}, ZO{}, Full{});
             iter(t + 1, S1{}, ZO{}, Full{});
             iter(t + 2, S2{}, ZO{}, Full{});
         }
+        iter(t, S0{}, ZO{}, Full{});
+        iter(t + 1, S1{}, ZO{}, Full{});
+        iter(t + 2, S2{}, ZO{}, std::integral_constant<int, kPartLast>{});
     }
 }
 
